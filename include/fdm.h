@@ -1,0 +1,213 @@
+/*
+ * fdm.h -- C ABI of the MI355X (gfx950) transport hot path for the layer case
+ * of field dislocation mechanics (Morin, Brenner & Suquet, arXiv:1911.03225).
+ *
+ * The library advances the two in-plane Nye dislocation-density components of
+ * the layer case (sec. 3.2.1) with the central-upwind Godunov-type scheme of
+ * sec. 3.2.2-3.2.3 on a periodic grid of pixel nodes.
+ *
+ * Units are the paper's dimensionless ones (sec. 3.2.1): lengths in b, times
+ * in b / V_s, densities as b * alpha, celerity v0 in V_s.
+ *
+ * Grid and layout.  nx by ny pixel nodes x_j = j dx, y_k = k dy (sec. 3.2.3),
+ * periodic in both directions; nx, ny >= 1 (ny = 1 is a 1-D problem along x).
+ * Arrays are row-major, index k * nx + j, x fastest, float32, device memory:
+ *   alpha12[k*nx + j]  alpha_12 = d1 U^p_13 on the x-edge ((j+1/2) dx, k dy);
+ *   alpha11[k*nx + j]  alpha_11 = -d2 U^p_13 on the y-edge (j dx, (k+1/2) dy).
+ * These are the differences of U^p_13 between neighbouring nodes, so the
+ * conservative update used here is the node update of U^p_13 differenced
+ * along x and y: it keeps sum(alpha_11), sum(alpha_12) and the discrete
+ * div(alpha) = 0 (eq. 2) to round-off.
+ *
+ * Ownership.  Density arrays belong to the caller (e.g. torch tensors) and are
+ * updated in place, in stream order; alpha11 and alpha12 must not alias each
+ * other or another instance's arrays.  A v0 field belongs to the caller and
+ * must stay valid, unchanged, for the context's lifetime.  The library owns
+ * only its workspace (one stage buffer per instance, reduction partials and
+ * descriptor tables), allocated in fdm_transport_init and freed in
+ * fdm_destroy.
+ *
+ * Streams.  Every call enqueues work on the HIP stream given at init (NULL is
+ * the null stream) and returns without waiting, except where stated.  One
+ * context belongs to one stream; separate contexts are independent.
+ *
+ * Errors.  Every entry point returns an fdm_status; FDM_OK is 0.  The library
+ * never aborts, throws or prints.  Arguments are validated on the host before
+ * any HIP call.  A HIP failure returns FDM_ERR_DEVICE, keeps its message in
+ * the context (fdm_last_error) and is sticky: every later call on that
+ * context returns FDM_ERR_DEVICE until fdm_destroy.
+ */
+#ifndef FDM_H
+#define FDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fdm_status {
+    FDM_OK = 0,
+    FDM_ERR_INVALID_ARG = 1,   /* a descriptor field or pointer is invalid        */
+    FDM_ERR_DEVICE = 2,        /* a HIP call failed (sticky, see fdm_last_error)  */
+    FDM_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed                     */
+    FDM_ERR_CFL = 4,           /* a fixed dt exceeds the Courant-number-1 bound   */
+    FDM_ERR_NONFINITE = 5,     /* a NaN or Inf was found in the densities         */
+    FDM_ERR_UNSUPPORTED = 6    /* feature not available in this build             */
+} fdm_status;
+
+/* Step 1 limiters (sec. 3.2.2, limited second difference of U^p_13, i.e.
+ * the limited slope of each density component along its own axis):
+ * minmod(theta D+, (D+ + D-)/2, theta D-) with theta = 1 (MINMOD), theta = 2
+ * (MC) or a given theta in [1, 2] (THETA); SUPERBEE is Roe's superbee (not in
+ * the paper); NONE gives the first-order scheme. */
+typedef enum fdm_limiter {
+    FDM_LIMITER_NONE = 0,
+    FDM_LIMITER_MINMOD = 1,
+    FDM_LIMITER_MC = 2,
+    FDM_LIMITER_THETA = 3,
+    FDM_LIMITER_SUPERBEE = 4
+} fdm_limiter;
+
+/* Hamiltonian.  LAW: H = v0 |grad U^p_13| (eq. 52 and 56), the layer-case
+ * velocity law with the celerity v0 at the nodes (a uniform value or a field;
+ * v0 = 0 marks immobile nodes, e.g. eta = infinity in precipitates, sec. 5.3).
+ * PRESCRIBED: H = V . grad U^p_13 with a uniform V (eq. 28 with only U^p_13
+ * non-zero), for verification. */
+typedef enum fdm_velocity {
+    FDM_VELOCITY_LAW = 0,
+    FDM_VELOCITY_PRESCRIBED = 1
+} fdm_velocity;
+
+/* One transport problem. */
+typedef struct fdm_transport_desc {
+    int32_t nx, ny;          /* pixel nodes, >= 1 each; nx*ny < 2^31             */
+    double dx, dy;           /* grid spacings, > 0                              */
+    int32_t limiter;         /* fdm_limiter                                     */
+    double theta;            /* FDM_LIMITER_THETA only, in [1, 2]               */
+    int32_t time_order;      /* 1: one forward-Euler stage of the semi-discrete
+                                scheme; 2: two-stage SSP Runge-Kutta (Heun),
+                                the default when 0 is given                      */
+    double cfl;              /* Courant number nu in (0, 1] used when dt == 0   */
+    double dt;               /* 0: dt = nu min(dx,dy) / s_max rounded down to a
+                                float; > 0: this step (rounded to the nearest
+                                float), rejected with FDM_ERR_CFL if
+                                dt s_max / min(dx,dy) > 1                        */
+    int32_t velocity;        /* fdm_velocity                                    */
+    double v0;               /* LAW: uniform celerity when v0_field is NULL     */
+    const float *v0_field;   /* LAW: device array of nx*ny node celerities, or
+                                NULL; s_max = max |v0| over the field           */
+    double V[2];             /* PRESCRIBED: velocity (V1, V2)                   */
+} fdm_transport_desc;
+
+/* Scheduling options; pass NULL for the defaults. */
+typedef enum fdm_schedule {
+    FDM_SCHEDULE_AUTO = 0,     /* batched launches when n_instances > 1        */
+    FDM_SCHEDULE_BATCHED = 1,  /* one launch per stage for all instances       */
+    FDM_SCHEDULE_PLAIN = 2     /* one launch per stage per instance            */
+} fdm_schedule;
+
+typedef struct fdm_options {
+    int32_t schedule;        /* fdm_schedule                                    */
+    int32_t tile_rows;       /* rows per wave tile; 0 picks a default           */
+    int32_t fused;           /* time_order 2: 0 auto, 1 fused step kernel,
+                                -1 two stage kernels                            */
+    int32_t reserved;
+} fdm_options;
+
+/* Per-instance diagnostics (FP64, deterministic: fixed-order compensated
+ * reductions). */
+typedef struct fdm_stats {
+    double t;                /* simulated time: step * dt                       */
+    double dt;               /* the float32 step actually used                  */
+    int64_t step;            /* steps taken since init                          */
+    double sum11, sum12;     /* sum over edges of alpha_11, alpha_12            */
+    double sum_abs;          /* sum over edges of |alpha_11| + |alpha_12|       */
+    double max_norm;         /* max over k*nx+j of sqrt(a11^2 + a12^2)          */
+    double drift11, drift12; /* sum11, sum12 minus their values at the first
+                                stats evaluation of this context                */
+    int64_t nonfinite;       /* number of index pairs with a NaN or Inf         */
+} fdm_stats;
+
+typedef struct fdm_ctx fdm_ctx;
+
+/* Set up n_instances >= 1 independent problems (descs[i]) on one stream.
+ * Validates every descriptor on the host, computes s_max (max |v0| over the
+ * node field on the device, or |v0|, or max(|V1|/dx, |V2|/dy) min(dx,dy)) and
+ * dt from the Courant number (sec. 4.3: |v0| dt / dx fixed), allocates the
+ * workspace and chooses tiles.  Waits for its own device work before
+ * returning.  On any error *out is set to NULL and nothing is leaked. */
+fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instances,
+                              const fdm_options *options, void *hip_stream,
+                              fdm_ctx **out);
+
+/* Enqueue n_steps >= 0 time steps of every instance.  alpha11[i], alpha12[i]
+ * are the device arrays of instance i (see layout above); they are read and
+ * written in place.  Asynchronous: returns after enqueueing. */
+fdm_status fdm_transport_step(fdm_ctx *ctx, float *const *alpha11,
+                              float *const *alpha12, int32_t n_steps);
+
+/* Diagnostics of every instance's current state into out[0..n_instances-1]
+ * (sums, norms, non-finite count; see fdm_stats).  Synchronizes the stream.
+ * Returns FDM_ERR_NONFINITE (after filling out) if any instance holds a NaN
+ * or Inf. */
+fdm_status fdm_transport_stats(fdm_ctx *ctx, float *const *alpha11,
+                               float *const *alpha12, fdm_stats *out);
+
+/* Static problem (sec. 3.1.2): layer-averaged shear stress tau_13 (sec.
+ * 3.2.1) of a homogeneous isotropic cell for given layer densities. */
+typedef struct fdm_static_desc {
+    int32_t nx, ny;          /* layer grid (as in fdm_transport_desc)           */
+    double dx, dy;
+    double mu, lambda;       /* elastic constants (dimensionless: mu = 1)       */
+    double layer_h;          /* layer thickness                                 */
+    double cell_l3;          /* cell height along x3                            */
+    double eps13;            /* macroscopic shear strain                        */
+} fdm_static_desc;
+
+/* Writes tau13_out[k*nx + j] at the nodes.  Returns FDM_ERR_UNSUPPORTED in
+ * this build. */
+fdm_status fdm_static_solve(const fdm_static_desc *desc, const float *alpha11,
+                            const float *alpha12, float *tau13_out, void *hip_stream);
+
+/* Coupled loading for fdm_run (sec. 3.1.1 alternating static/evolution
+ * split); reserved. */
+typedef struct fdm_loading {
+    double strain_rate13;    /* macroscopic shear strain rate                   */
+    double tau0;             /* threshold stress                                */
+    double mobility;         /* 1 / eta (dimensionless)                         */
+    double mu, lambda, layer_h, cell_l3;
+    double dt_max;           /* upper bound on the adaptive step                */
+} fdm_loading;
+
+/* Run n_steps in chunks of `chunk` steps (the last chunk may be shorter).
+ * loading == NULL: uncoupled transport; each chunk is replayed from a
+ * captured HIP graph and history[c] receives the stats after chunk c
+ * (history needs ceil(n_steps/chunk) * n_instances records, instance-major
+ * within a chunk).  history may be NULL.  Synchronizes the stream once per
+ * chunk when history is given, once at the end otherwise.
+ * loading != NULL (coupled) returns FDM_ERR_UNSUPPORTED in this build. */
+fdm_status fdm_run(fdm_ctx *ctx, const fdm_loading *loading, float *const *alpha11,
+                   float *const *alpha12, int32_t n_steps, int32_t chunk,
+                   fdm_stats *history);
+
+/* The float32 time step of instance i (after init), or -1 on a bad argument. */
+double fdm_transport_dt(const fdm_ctx *ctx, int32_t instance);
+
+/* Release the context and its workspace (waits for its pending work).
+ * NULL is a no-op. */
+void fdm_destroy(fdm_ctx *ctx);
+
+/* Static description of a status code. */
+const char *fdm_status_string(fdm_status status);
+
+/* Message of the last error on this context ("" if none); valid until the
+ * next call on the context.  ctx == NULL gives the last error of a failed
+ * fdm_transport_init on this thread. */
+const char *fdm_last_error(const fdm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDM_H */

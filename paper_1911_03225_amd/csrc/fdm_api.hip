@@ -1,0 +1,513 @@
+// fdm_api.hip -- C ABI (include/fdm.h) of the gfx950 transport hot path.
+//
+// Host-side responsibilities: validate descriptors before any HIP call,
+// compute the CFL-bounded step from max |v0| (a device reduction for a
+// celerity field), own the per-instance stage buffers and reduction
+// scratch, sequence the stage launches (two per Heun step), replay captured
+// HIP graphs for fdm_run, and keep a sticky error per context.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fdm.h"
+#include "fdm_internal.h"
+
+using fdm::InstDev;
+
+struct fdm_ctx {
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;          // private stream for graph capture
+    int32_t n = 0;
+    int32_t time_order = 2;
+    int32_t schedule = FDM_SCHEDULE_AUTO;
+    bool batched = false;
+    std::vector<fdm_transport_desc> desc;
+    std::vector<InstDev> inst;              // host copies of the device views
+    std::vector<float> dt;                  // float32 step per instance
+    float *workspace = nullptr;             // all stage buffers
+    InstDev *d_inst = nullptr;              // batched: device table
+    InstDev *h_inst_pinned = nullptr;       // staging for table uploads
+    int32_t *d_tile_inst = nullptr;         // batched: tile -> instance
+    int64_t total_tiles = 0;
+    fdm::StatsPartial *d_partials = nullptr;
+    double *d_stats = nullptr;              // 5 doubles per instance
+    double *h_stats = nullptr;              // pinned copy
+    float *d_absmax = nullptr;
+    bool table_valid = false;
+    bool have_ref = false;
+    std::vector<double> ref11, ref12;
+    int64_t steps = 0;
+    // graph cache for fdm_run
+    hipGraphExec_t graph = nullptr;
+    int32_t graph_steps = 0;
+    std::vector<float *> graph_a11, graph_a12;
+    bool sticky = false;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+fdm_status fail(fdm_ctx *c, fdm_status st, const std::string &msg)
+{
+    if (c) {
+        c->err = msg;
+        if (st == FDM_ERR_DEVICE) c->sticky = true;
+    } else {
+        g_init_error = msg;
+    }
+    return st;
+}
+
+#define FDM_HIP(ctx, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE, \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                  \
+        }                                                                                   \
+    } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Host-side validation of one descriptor (no HIP call).
+std::string check_desc(const fdm_transport_desc &d)
+{
+    if (d.nx < 1 || d.ny < 1) return "nx and ny must be >= 1";
+    if ((int64_t)d.nx * d.ny >= (int64_t)1 << 31) return "nx*ny must be < 2^31";
+    if (!finite_pos(d.dx) || !finite_pos(d.dy)) return "dx and dy must be finite and > 0";
+    if (d.limiter < FDM_LIMITER_NONE || d.limiter > FDM_LIMITER_SUPERBEE) return "unknown limiter";
+    if (d.limiter == FDM_LIMITER_THETA && !(d.theta >= 1.0 && d.theta <= 2.0))
+        return "theta must lie in [1, 2]";
+    if (d.time_order != 0 && d.time_order != 1 && d.time_order != 2) return "time_order must be 1 or 2";
+    if (!(std::isfinite(d.dt) && d.dt >= 0.0)) return "dt must be finite and >= 0";
+    if (d.dt == 0.0 && !(d.cfl > 0.0 && d.cfl <= 1.0)) return "cfl must lie in (0, 1]";
+    if (d.velocity != FDM_VELOCITY_LAW && d.velocity != FDM_VELOCITY_PRESCRIBED)
+        return "unknown velocity kind";
+    if (d.velocity == FDM_VELOCITY_LAW && d.v0_field == nullptr && !std::isfinite(d.v0))
+        return "v0 must be finite";
+    if (d.velocity == FDM_VELOCITY_PRESCRIBED && !(std::isfinite(d.V[0]) && std::isfinite(d.V[1])))
+        return "V must be finite";
+    return "";
+}
+
+// Largest float not above x (x > 0).
+float round_down_float(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, 0.0f);
+    return f;
+}
+
+// Rows per wave tile: enough waves to fill 256 CUs several times over.
+int pick_rows(const fdm_transport_desc &d, int requested)
+{
+    if (requested > 0) return std::min(requested, d.ny);
+    const int64_t strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
+    int rows = 32;
+    while (rows > 4 && strips * ((d.ny + rows - 1) / rows) < 16384) rows >>= 1;
+    return std::min(rows, d.ny);
+}
+
+void release(fdm_ctx *c)
+{
+    if (!c) return;
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->workspace) (void)hipFree(c->workspace);
+    if (c->d_inst) (void)hipFree(c->d_inst);
+    if (c->d_tile_inst) (void)hipFree(c->d_tile_inst);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_stats) (void)hipFree(c->d_stats);
+    if (c->d_absmax) (void)hipFree(c->d_absmax);
+    if (c->h_stats) (void)hipHostFree(c->h_stats);
+    if (c->h_inst_pinned) (void)hipHostFree(c->h_inst_pinned);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    delete c;
+}
+
+fdm_status check_ptrs(fdm_ctx *c, float *const *a11, float *const *a12)
+{
+    if (!a11 || !a12) return fail(c, FDM_ERR_INVALID_ARG, "alpha11/alpha12 pointer arrays must not be NULL");
+    for (int i = 0; i < c->n; ++i) {
+        if (!a11[i] || !a12[i]) return fail(c, FDM_ERR_INVALID_ARG, "NULL density array for instance " + std::to_string(i));
+        if (a11[i] == a12[i]) return fail(c, FDM_ERR_INVALID_ARG, "alpha11 and alpha12 alias for instance " + std::to_string(i));
+    }
+    return FDM_OK;
+}
+
+// Point the device views at this call's arrays; re-upload the batched table
+// when they changed.
+fdm_status bind(fdm_ctx *c, float *const *a11, float *const *a12)
+{
+    bool changed = !c->table_valid;
+    for (int i = 0; i < c->n; ++i) {
+        if (c->inst[i].a11 != a11[i] || c->inst[i].a12 != a12[i]) changed = true;
+        c->inst[i].a11 = a11[i];
+        c->inst[i].a12 = a12[i];
+    }
+    if (c->batched && changed) {
+        // the staging buffer may still feed an earlier upload
+        FDM_HIP(c, hipStreamSynchronize(c->stream));
+        std::memcpy(c->h_inst_pinned, c->inst.data(), sizeof(InstDev) * c->n);
+        FDM_HIP(c, hipMemcpyAsync(c->d_inst, c->h_inst_pinned, sizeof(InstDev) * c->n,
+                                  hipMemcpyHostToDevice, c->stream));
+    }
+    c->table_valid = true;
+    return FDM_OK;
+}
+
+// Enqueue n_steps on stream s for the bound arrays.
+fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
+{
+    for (int32_t step = 0; step < n_steps; ++step) {
+        int modes[2];
+        int nm;
+        if (c->time_order == 2) {
+            modes[0] = fdm::MODE_FWD;
+            modes[1] = fdm::MODE_HEUN2;
+            nm = 2;
+        } else {
+            modes[0] = (step & 1) ? fdm::MODE_BWD : fdm::MODE_FWD;
+            nm = 1;
+        }
+        for (int m = 0; m < nm; ++m) {
+            if (c->batched) {
+                FDM_HIP(c, fdm::launch_stage_batched(c->d_inst, c->d_tile_inst, c->total_tiles, modes[m], s));
+            } else {
+                for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_stage(c->inst[i], modes[m], s));
+            }
+        }
+    }
+    // Euler ping-pongs between the state and the stage buffer; after an odd
+    // count the newest state sits in the stage buffer.
+    if (c->time_order == 1 && (n_steps & 1)) {
+        for (int i = 0; i < c->n; ++i) {
+            const int64_t n = (int64_t)c->inst[i].nx * c->inst[i].ny;
+            FDM_HIP(c, fdm::launch_copy(c->inst[i].a11, c->inst[i].w11, n, s));
+            FDM_HIP(c, fdm::launch_copy(c->inst[i].a12, c->inst[i].w12, n, s));
+        }
+    }
+    return FDM_OK;
+}
+
+fdm_status compute_stats(fdm_ctx *c, float *const *a11, float *const *a12, fdm_stats *out)
+{
+    for (int i = 0; i < c->n; ++i) {
+        const int64_t n = (int64_t)c->inst[i].nx * c->inst[i].ny;
+        FDM_HIP(c, fdm::launch_stats(a11[i], a12[i], n, c->d_partials, c->d_stats + 5 * i, c->stream));
+    }
+    FDM_HIP(c, hipMemcpyAsync(c->h_stats, c->d_stats, sizeof(double) * 5 * c->n, hipMemcpyDeviceToHost,
+                              c->stream));
+    FDM_HIP(c, hipStreamSynchronize(c->stream));
+    if (!c->have_ref) {
+        c->ref11.resize(c->n);
+        c->ref12.resize(c->n);
+        for (int i = 0; i < c->n; ++i) {
+            c->ref11[i] = c->h_stats[5 * i + 0];
+            c->ref12[i] = c->h_stats[5 * i + 1];
+        }
+        c->have_ref = true;
+    }
+    bool bad = false;
+    for (int i = 0; i < c->n; ++i) {
+        const double *h = c->h_stats + 5 * i;
+        fdm_stats &o = out[i];
+        o.dt = c->dt[i];
+        o.step = c->steps;
+        o.t = (double)c->steps * (double)c->dt[i];
+        o.sum11 = h[0];
+        o.sum12 = h[1];
+        o.sum_abs = h[2];
+        o.max_norm = h[3];
+        o.nonfinite = (int64_t)h[4];
+        o.drift11 = h[0] - c->ref11[i];
+        o.drift12 = h[1] - c->ref12[i];
+        bad |= o.nonfinite != 0;
+    }
+    if (bad) return fail(c, FDM_ERR_NONFINITE, "non-finite density values found");
+    return FDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instances, const fdm_options *options,
+                              void *hip_stream, fdm_ctx **out)
+{
+    if (!out) return fail(nullptr, FDM_ERR_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    if (!descs || n_instances < 1) return fail(nullptr, FDM_ERR_INVALID_ARG, "need at least one descriptor");
+    fdm_options opt = {0, 0, 0, 0};
+    if (options) opt = *options;
+    if (opt.schedule < FDM_SCHEDULE_AUTO || opt.schedule > FDM_SCHEDULE_PLAIN)
+        return fail(nullptr, FDM_ERR_INVALID_ARG, "unknown schedule");
+    if (opt.tile_rows < 0) return fail(nullptr, FDM_ERR_INVALID_ARG, "tile_rows must be >= 0");
+    int32_t order = -1;
+    for (int i = 0; i < n_instances; ++i) {
+        const std::string m = check_desc(descs[i]);
+        if (!m.empty()) return fail(nullptr, FDM_ERR_INVALID_ARG, "descriptor " + std::to_string(i) + ": " + m);
+        const int32_t o = descs[i].time_order == 0 ? 2 : descs[i].time_order;
+        if (order >= 0 && o != order)
+            return fail(nullptr, FDM_ERR_INVALID_ARG, "all instances of a context must share time_order");
+        order = o;
+    }
+    // Courant bound of a fixed dt needs s_max; uniform cases are checked here,
+    // field cases after the device reduction below.
+    fdm_ctx *c = new (std::nothrow) fdm_ctx;
+    if (!c) return fail(nullptr, FDM_ERR_OUT_OF_MEMORY, "host allocation failed");
+    c->stream = (hipStream_t)hip_stream;
+    c->n = n_instances;
+    c->time_order = order;
+    c->schedule = opt.schedule;
+    c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN;
+    c->desc.assign(descs, descs + n_instances);
+    c->inst.resize(n_instances);
+    c->dt.resize(n_instances);
+
+    auto bail = [&](fdm_status st) {
+        g_init_error = c->err;
+        release(c);
+        return st;
+    };
+#define INIT_HIP(call)                                                                            \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            fail(c, e_ == hipErrorOutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE,           \
+                 std::string(#call) + ": " + hipGetErrorString(e_));                              \
+            return bail(e_ == hipErrorOutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE);       \
+        }                                                                                         \
+    } while (0)
+
+    // workspace: one stage buffer (both components) per instance
+    int64_t total = 0;
+    for (int i = 0; i < n_instances; ++i) total += 2 * (int64_t)descs[i].nx * descs[i].ny;
+    INIT_HIP(hipMalloc((void **)&c->workspace, sizeof(float) * total));
+    INIT_HIP(hipMalloc((void **)&c->d_partials, sizeof(fdm::StatsPartial) * fdm::kStatsBlocks));
+    INIT_HIP(hipMalloc((void **)&c->d_stats, sizeof(double) * 5 * n_instances));
+    INIT_HIP(hipHostMalloc((void **)&c->h_stats, sizeof(double) * 5 * n_instances, hipHostMallocDefault));
+    INIT_HIP(hipMalloc((void **)&c->d_absmax, sizeof(float) * fdm::kAbsmaxBlocks));
+
+    std::vector<float> absmax(fdm::kAbsmaxBlocks);
+    int64_t off = 0, tile = 0;
+    for (int i = 0; i < n_instances; ++i) {
+        const fdm_transport_desc &d = descs[i];
+        const int64_t n = (int64_t)d.nx * d.ny;
+        const double h = std::min(d.dx, d.dy);
+        double smax;
+        if (d.velocity == FDM_VELOCITY_PRESCRIBED) {
+            smax = std::max(std::fabs(d.V[0]) / d.dx, std::fabs(d.V[1]) / d.dy) * h;
+        } else if (d.v0_field) {
+            INIT_HIP(fdm::launch_absmax(d.v0_field, n, c->d_absmax, c->stream));
+            INIT_HIP(hipMemcpyAsync(absmax.data(), c->d_absmax, sizeof(float) * fdm::kAbsmaxBlocks,
+                                    hipMemcpyDeviceToHost, c->stream));
+            INIT_HIP(hipStreamSynchronize(c->stream));
+            float m = 0.0f;
+            for (float v : absmax) {
+                if (std::isnan(v)) {
+                    fail(c, FDM_ERR_INVALID_ARG, "v0_field of descriptor " + std::to_string(i) + " is not finite");
+                    return bail(FDM_ERR_INVALID_ARG);
+                }
+                m = std::max(m, v);
+            }
+            smax = m;
+        } else {
+            smax = std::fabs((double)(float)d.v0);
+        }
+        float dt;
+        if (d.dt > 0.0) {
+            dt = (float)d.dt;
+            if ((double)dt * smax / h > 1.0) {
+                fail(c, FDM_ERR_CFL, "dt of descriptor " + std::to_string(i) + " exceeds the Courant-number-1 bound");
+                return bail(FDM_ERR_CFL);
+            }
+        } else {
+            dt = round_down_float(smax > 0.0 ? d.cfl * h / smax : d.cfl * h);
+        }
+        c->dt[i] = dt;
+
+        InstDev &I = c->inst[i];
+        std::memset(&I, 0, sizeof(I));
+        I.w11 = c->workspace + off;
+        I.w12 = c->workspace + off + n;
+        off += 2 * n;
+        I.v0f = d.velocity == FDM_VELOCITY_LAW ? d.v0_field : nullptr;
+        I.nx = d.nx;
+        I.ny = d.ny;
+        I.v0 = (float)d.v0;
+        I.V1 = (float)d.V[0];
+        I.V2 = (float)d.V[1];
+        I.cx = (float)((double)dt / d.dx);
+        I.cy = (float)((double)dt / d.dy);
+        I.theta = d.limiter == FDM_LIMITER_MINMOD ? 1.0f : d.limiter == FDM_LIMITER_MC ? 2.0f : (float)d.theta;
+        I.limiter = d.limiter;
+        I.vkind = d.velocity;
+        I.rows = pick_rows(d, opt.tile_rows);
+        I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
+        I.chunks = (d.ny + I.rows - 1) / I.rows;
+        I.tile_begin = tile;
+        tile += (int64_t)I.strips * I.chunks;
+    }
+    c->total_tiles = tile;
+    if (c->batched) {
+        if (tile >= ((int64_t)1 << 31)) {
+            fail(c, FDM_ERR_INVALID_ARG, "too many tiles for one batched launch");
+            return bail(FDM_ERR_INVALID_ARG);
+        }
+        std::vector<int32_t> map(tile);
+        for (int i = 0; i < n_instances; ++i) {
+            const int64_t b = c->inst[i].tile_begin, e = b + (int64_t)c->inst[i].strips * c->inst[i].chunks;
+            for (int64_t t = b; t < e; ++t) map[t] = i;
+        }
+        INIT_HIP(hipMalloc((void **)&c->d_tile_inst, sizeof(int32_t) * tile));
+        INIT_HIP(hipMemcpy(c->d_tile_inst, map.data(), sizeof(int32_t) * tile, hipMemcpyHostToDevice));
+        INIT_HIP(hipMalloc((void **)&c->d_inst, sizeof(InstDev) * n_instances));
+        INIT_HIP(hipHostMalloc((void **)&c->h_inst_pinned, sizeof(InstDev) * n_instances, hipHostMallocDefault));
+    }
+    INIT_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+#undef INIT_HIP
+    *out = c;
+    return FDM_OK;
+}
+
+fdm_status fdm_transport_step(fdm_ctx *c, float *const *alpha11, float *const *alpha12, int32_t n_steps)
+{
+    if (!c) return FDM_ERR_INVALID_ARG;
+    if (c->sticky) return FDM_ERR_DEVICE;
+    if (n_steps < 0) return fail(c, FDM_ERR_INVALID_ARG, "n_steps must be >= 0");
+    fdm_status st = check_ptrs(c, alpha11, alpha12);
+    if (st != FDM_OK) return st;
+    if (n_steps == 0) return FDM_OK;
+    st = bind(c, alpha11, alpha12);
+    if (st != FDM_OK) return st;
+    st = enqueue_steps(c, n_steps, c->stream);
+    if (st != FDM_OK) return st;
+    c->steps += n_steps;
+    return FDM_OK;
+}
+
+fdm_status fdm_transport_stats(fdm_ctx *c, float *const *alpha11, float *const *alpha12, fdm_stats *out)
+{
+    if (!c) return FDM_ERR_INVALID_ARG;
+    if (c->sticky) return FDM_ERR_DEVICE;
+    if (!out) return fail(c, FDM_ERR_INVALID_ARG, "out must not be NULL");
+    fdm_status st = check_ptrs(c, alpha11, alpha12);
+    if (st != FDM_OK) return st;
+    return compute_stats(c, alpha11, alpha12, out);
+}
+
+fdm_status fdm_static_solve(const fdm_static_desc *desc, const float *alpha11, const float *alpha12,
+                            float *tau13_out, void *hip_stream)
+{
+    (void)desc;
+    (void)alpha11;
+    (void)alpha12;
+    (void)tau13_out;
+    (void)hip_stream;
+    g_init_error = "the static FFT solve is not available in this build";
+    return FDM_ERR_UNSUPPORTED;
+}
+
+fdm_status fdm_run(fdm_ctx *c, const fdm_loading *loading, float *const *alpha11, float *const *alpha12,
+                   int32_t n_steps, int32_t chunk, fdm_stats *history)
+{
+    if (!c) return FDM_ERR_INVALID_ARG;
+    if (c->sticky) return FDM_ERR_DEVICE;
+    if (loading) return fail(c, FDM_ERR_UNSUPPORTED, "coupled runs are not available in this build");
+    if (n_steps < 0 || chunk < 1) return fail(c, FDM_ERR_INVALID_ARG, "need n_steps >= 0 and chunk >= 1");
+    fdm_status st = check_ptrs(c, alpha11, alpha12);
+    if (st != FDM_OK) return st;
+    if (n_steps == 0) return FDM_OK;
+    st = bind(c, alpha11, alpha12);
+    if (st != FDM_OK) return st;
+
+    // (Re)capture a graph of `chunk` steps for these arrays.
+    bool same = c->graph && c->graph_steps == chunk;
+    for (int i = 0; same && i < c->n; ++i)
+        same = c->graph_a11[i] == alpha11[i] && c->graph_a12[i] == alpha12[i];
+    if (!same) {
+        if (c->graph) {
+            FDM_HIP(c, hipGraphExecDestroy(c->graph));
+            c->graph = nullptr;
+        }
+        // the capture stream must see the table upload done by bind()
+        FDM_HIP(c, hipStreamSynchronize(c->stream));
+        hipGraph_t g = nullptr;
+        FDM_HIP(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+        fdm_status cs = enqueue_steps(c, chunk, c->capture);
+        hipError_t ee = hipStreamEndCapture(c->capture, &g);
+        if (cs != FDM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs;
+        }
+        if (ee != hipSuccess) return fail(c, FDM_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        hipError_t ie = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(c, FDM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        c->graph_steps = chunk;
+        c->graph_a11.assign(alpha11, alpha11 + c->n);
+        c->graph_a12.assign(alpha12, alpha12 + c->n);
+    }
+    int32_t done = 0, rec = 0;
+    while (done < n_steps) {
+        const int32_t m = std::min(chunk, n_steps - done);
+        if (m == chunk) {
+            FDM_HIP(c, hipGraphLaunch(c->graph, c->stream));
+        } else {
+            st = enqueue_steps(c, m, c->stream);
+            if (st != FDM_OK) return st;
+        }
+        done += m;
+        c->steps += m;
+        if (history) {
+            st = compute_stats(c, alpha11, alpha12, history + (int64_t)rec * c->n);
+            if (st != FDM_OK) return st;
+        }
+        ++rec;
+    }
+    if (!history) FDM_HIP(c, hipStreamSynchronize(c->stream));
+    return FDM_OK;
+}
+
+double fdm_transport_dt(const fdm_ctx *c, int32_t i)
+{
+    if (!c || i < 0 || i >= c->n) return -1.0;
+    return (double)c->dt[i];
+}
+
+void fdm_destroy(fdm_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+}
+
+const char *fdm_status_string(fdm_status s)
+{
+    switch (s) {
+    case FDM_OK: return "ok";
+    case FDM_ERR_INVALID_ARG: return "invalid argument";
+    case FDM_ERR_DEVICE: return "HIP device error";
+    case FDM_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case FDM_ERR_CFL: return "time step above the Courant-number-1 bound";
+    case FDM_ERR_NONFINITE: return "non-finite densities";
+    case FDM_ERR_UNSUPPORTED: return "unsupported in this build";
+    }
+    return "unknown status";
+}
+
+const char *fdm_last_error(const fdm_ctx *c)
+{
+    if (!c) return g_init_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// fdm_internal.h -- shared between the gfx950 kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdm {
+
+// Wave tiling of the stencil kernels.  One wave64 owns a strip of kStrip
+// consecutive columns plus kHalo columns on each side (the x stencil reaches
+// two edges each way) and walks a chunk of `rows` rows downwards, keeping the
+// y stencil in registers.
+constexpr int kWave = 64;
+constexpr int kHalo = 2;
+constexpr int kStrip = kWave - 2 * kHalo;   // 60 output columns per wave
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+// Limiter and Hamiltonian codes (values of the public enums).
+enum : int { LIM_NONE = 0, LIM_MINMOD = 1, LIM_MC = 2, LIM_THETA = 3, LIM_SUPERBEE = 4 };
+enum : int { VK_LAW = 0, VK_PRESCRIBED = 1 };
+
+// What one stage launch reads and writes.
+//   MODE_FWD   : w = a + dt L(a)                 (first stage / Euler step)
+//   MODE_BWD   : a = w + dt L(w)                 (Euler step, other direction)
+//   MODE_HEUN2 : a = a/2 + (w + dt L(w))/2       (second Heun stage, in place)
+enum : int { MODE_FWD = 0, MODE_BWD = 1, MODE_HEUN2 = 2 };
+
+// Device view of one transport instance.
+struct InstDev {
+    float *a11, *a12;        // state, caller-owned
+    float *w11, *w12;        // stage buffer, library-owned
+    const float *v0f;        // node celerity field or nullptr
+    int32_t nx, ny;
+    float v0, V1, V2;        // uniform celerity / prescribed velocity
+    float cx, cy;            // dt/dx, dt/dy
+    float theta;             // minmod-family parameter
+    int32_t limiter, vkind;
+    int32_t rows;            // rows per wave tile
+    int32_t strips, chunks;  // tiles along x and y
+    int32_t pad;
+    int64_t tile_begin;      // first global tile of this instance (batched)
+};
+
+// Per-block partial of the diagnostics reduction (compensated sums).
+struct StatsPartial {
+    double s11, c11, s12, c12, sab, cab, maxn, nonfinite;
+};
+
+constexpr int kStatsBlocks = 128;   // fixed => deterministic reduction order
+
+hipError_t launch_stage(const InstDev &I, int mode, hipStream_t s);
+hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst,
+                                int64_t total_tiles, int mode, hipStream_t s);
+hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s);
+hipError_t launch_stats(const float *a11, const float *a12, int64_t n,
+                        StatsPartial *d_partials, double *d_out, hipStream_t s);
+hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
+
+constexpr int kAbsmaxBlocks = 256;
+
+}  // namespace fdm

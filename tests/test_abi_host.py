@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function include/fdm.h declares, and
+reject invalid descriptors on the host before any HIP call.
+"""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    from paper_1911_03225_amd import fdm as F
+    if not os.path.exists(F.LIB_PATH):
+        from paper_1911_03225_amd import build
+        build.build()
+    F.load_library()
+    return F
+
+
+def test_exports_every_declared_function(fdm):
+    names = fdm.header_functions()
+    assert {"fdm_transport_init", "fdm_transport_step", "fdm_static_solve", "fdm_run"} <= set(names)
+    lib = fdm.load_library()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_header_enums_match_binding(fdm):
+    text = open(os.path.join(ROOT, "include", "fdm.h")).read()
+    vals = dict((k, int(v)) for k, v in re.findall(r"\b(FDM_\w+)\s*=\s*(\d+)", text))
+    assert vals["FDM_OK"] == fdm.FDM_OK
+    assert vals["FDM_ERR_INVALID_ARG"] == fdm.FDM_ERR_INVALID_ARG
+    assert vals["FDM_ERR_DEVICE"] == fdm.FDM_ERR_DEVICE
+    assert vals["FDM_ERR_CFL"] == fdm.FDM_ERR_CFL
+    assert vals["FDM_ERR_NONFINITE"] == fdm.FDM_ERR_NONFINITE
+    assert vals["FDM_ERR_UNSUPPORTED"] == fdm.FDM_ERR_UNSUPPORTED
+    for name, v in fdm.LIMITERS.items():
+        assert vals["FDM_LIMITER_" + name.upper()] == v
+    assert vals["FDM_VELOCITY_LAW"] == fdm.VELOCITIES["law"]
+    assert vals["FDM_VELOCITY_PRESCRIBED"] == fdm.VELOCITIES["prescribed"]
+
+
+def test_struct_sizes_match_c_layout(fdm):
+    import ctypes
+    # int32 + pad before each double, pointer-aligned field: the C layout
+    assert ctypes.sizeof(fdm.fdm_transport_desc) == 104
+    assert ctypes.sizeof(fdm.fdm_stats) == 80
+    assert ctypes.sizeof(fdm.fdm_options) == 16
+
+
+def test_status_strings(fdm):
+    for st in range(7):
+        assert fdm.fdm_status_string(st)
+    assert fdm.fdm_status_string(99) == "unknown status"
+
+
+BAD = [
+    (dict(nx=0), "nx and ny"),
+    (dict(ny=-3), "nx and ny"),
+    (dict(nx=65536, ny=65536), "2^31"),
+    (dict(dx=0.0), "dx and dy"),
+    (dict(dy=float("nan")), "dx and dy"),
+    (dict(limiter=7), "limiter"),
+    (dict(limiter="theta", theta=2.5), "theta"),
+    (dict(limiter="theta", theta=0.9), "theta"),
+    (dict(time_order=3), "time_order"),
+    (dict(cfl=0.0), "cfl"),
+    (dict(cfl=1.5), "cfl"),
+    (dict(dt=-1.0), "dt"),
+    (dict(velocity=5), "velocity"),
+    (dict(v0=float("inf")), "v0"),
+    (dict(velocity="prescribed", V=(float("nan"), 0.0)), "V"),
+]
+
+
+@pytest.mark.parametrize("kw,msg", BAD)
+def test_invalid_descriptor_rejected_on_host(fdm, kw, msg):
+    args = dict(nx=16, ny=16)
+    args.update(kw)
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init(fdm.desc(**args))
+    assert e.value.status == fdm.FDM_ERR_INVALID_ARG
+    assert msg in fdm.fdm_last_error(None)
+
+
+def test_mixed_time_orders_rejected(fdm):
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init([fdm.desc(8, 8, time_order=1), fdm.desc(8, 8, time_order=2)])
+    assert e.value.status == fdm.FDM_ERR_INVALID_ARG
+
+
+def test_null_arguments(fdm):
+    lib = fdm.load_library()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lib.fdm_transport_init(None, 1, None, None, ctypes.byref(h)) == fdm.FDM_ERR_INVALID_ARG
+    assert lib.fdm_transport_init(None, 1, None, None, None) == fdm.FDM_ERR_INVALID_ARG
+    assert lib.fdm_transport_step(None, None, None, 1) == fdm.FDM_ERR_INVALID_ARG
+    assert lib.fdm_run(None, None, None, None, 1, 1, None) == fdm.FDM_ERR_INVALID_ARG
+    assert fdm.load_library().fdm_transport_dt(None, 0) == -1.0
+    lib.fdm_destroy(None)   # no-op
+
+
+def test_static_solve_reports_unsupported(fdm):
+    import ctypes
+    lib = fdm.load_library()
+    d = fdm.fdm_static_desc()
+    assert lib.fdm_static_solve(ctypes.byref(d), None, None, None, None) == fdm.FDM_ERR_UNSUPPORTED
+
+
+def test_valid_descriptor_without_gpu_fails_cleanly(fdm):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init(fdm.desc(16, 16))
+    assert e.value.status == fdm.FDM_ERR_DEVICE

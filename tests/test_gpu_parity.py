@@ -1,0 +1,309 @@
+"""GPU (HIP, gfx950) path against the FP64 oracle, through the C ABI.
+
+Tolerance: relative L1 over both components, normalised by the initial L1
+norm, at most 1e-5 per started block of 1000 steps, checked at every
+snapshot (the FP32 path against the FP64 scheme on the same float32 inputs).
+Relative L-infinity is reported in the assertion messages but not gated: at
+shocks FP32 rounding moves a front sample by one ulp of the jump.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import compare_run, gpu_run, oracle_problem, rel_l1, to_dev, tolerance
+from exact_solutions import densities, ring_phi_exact
+from paper_1911_03225_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_03225_amd import fdm as F
+    F.load_library()
+    return F
+
+
+def _assert_report(report, n_total):
+    for s, e1, einf in report:
+        assert e1 <= tolerance(s), "step %d: rel L1 %.3e (rel Linf %.3e)" % (s, e1, einf)
+
+
+# --------------------------------------------------------------- C1 family
+
+@pytest.mark.parametrize("limiter", ["minmod", "mc", "superbee"])
+def test_c1_collision(fdm, oracle, limiter):
+    """64x64, opposite Gaussian pulses, LAW v0 = -1, Courant 0.5, 400 steps."""
+    a11, a12 = W.c1_collision(64)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 400, every=100, limiter=limiter, cfl=0.5, v0=-1.0)
+    assert dt == 0.5
+    _assert_report(rep, 400)
+    assert not np.any(g[0])                      # alpha_11 stays exactly 0
+
+
+def test_c1_exact_period(fdm, oracle):
+    """First order, one stage, Courant 1, V = (1, 0.5): exact return after 64 steps."""
+    a11, a12 = W.c1_exact_period(64)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 64, every=16, limiter="none", time_order=1,
+                                velocity="prescribed", V=(1.0, 0.5), cfl=1.0)
+    assert dt == 1.0
+    _assert_report(rep, 64)
+    assert np.max(np.abs(g[1] - a12)) <= 1e-6 * np.max(np.abs(a12))
+
+
+@pytest.mark.parametrize("steps", [7, 8])
+def test_single_stage_odd_even(fdm, oracle, steps):
+    a11, a12 = W.ring(96, 80, R=20.0, sigma=3.0)
+    dt, rep, g, o = compare_run(oracle, a11, a12, steps, limiter="minmod", time_order=1, cfl=0.25, v0=-1.0)
+    _assert_report(rep, steps)
+
+
+# ------------------------------------------------------------ ring (C2)
+
+@pytest.mark.parametrize("limiter", ["superbee", "mc"])
+def test_ring_1000_steps(fdm, oracle, limiter):
+    """C2 shape at 256^2 (R = 50, sigma = 6), Courant 0.4, 1000 steps."""
+    a11, a12 = W.ring(256, 256, R=50.0, sigma=6.0)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 1000, every=100, limiter=limiter, cfl=0.4, v0=-1.0)
+    assert dt == float(np.nextafter(np.float32(0.4), np.float32(0)))
+    _assert_report(rep, 1000)
+
+
+@pytest.mark.parametrize("limiter", ["superbee", "mc"])
+def test_c2_full_size_short(fdm, oracle, limiter):
+    """C2 at its full size (2048^2, R = 300, sigma = 6) for 12 steps, full grid."""
+    a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 12, every=6, limiter=limiter, cfl=0.4, v0=-1.0)
+    _assert_report(rep, 12)
+
+
+def test_c2_full_length_properties(fdm):
+    """C2 for its full 2000 steps (t ~ 800, past the collision with the
+    periodic images at t ~ 724): finite, conserved totals, no damping before
+    the collision, close to the Hopf-Lax solution at t = 400."""
+    from paper_1911_03225_amd import fdm as F
+    import torch
+    n, R, sigma = 2048, 300.0, 6.0
+    a11, a12 = W.ring(n, n, R=R, sigma=sigma)
+    t11, t12 = to_dev(a11), to_dev(a12)
+    ctx = F.fdm_transport_init(F.desc(n, n, limiter="superbee", cfl=0.4, v0=-1.0))
+    s0 = F.fdm_transport_stats(ctx, t11, t12)[0]
+    F.fdm_transport_step(ctx, t11, t12, 1000)
+    s1 = F.fdm_transport_stats(ctx, t11, t12)[0]
+    dt = F.fdm_transport_dt(ctx)
+    g11, g12 = t11.cpu().numpy().astype(np.float64), t12.cpu().numpy().astype(np.float64)
+    e11, e12 = densities(ring_phi_exact(n, float(n), R, sigma, 1000 * dt), 1.0, 1.0)
+    err = rel_l1(g11, g12, e11, e12, a11, a12)
+    peak = np.max(np.hypot(g11, g12)) / np.max(np.hypot(a11, a12))
+    F.fdm_transport_step(ctx, t11, t12, 1000)
+    s2 = F.fdm_transport_stats(ctx, t11, t12)[0]
+    torch.cuda.synchronize()
+    F.fdm_destroy(ctx)
+    assert s2["nonfinite"] == 0 and s2["step"] == 2000
+    for s in (s1, s2):
+        assert abs(s["drift11"]) <= 1e-5 * s0["sum_abs"] and abs(s["drift12"]) <= 1e-5 * s0["sum_abs"]
+    assert err < 0.05, err
+    assert 0.9 < peak < 1.05, peak
+
+
+# ------------------------------------------------- varying celerity (C3)
+
+def test_c3_shape_parity(fdm, oracle):
+    """Diagonal bands + Fourier celerity field (C3 recipe at 512^2), minmod,
+    Courant 0.45, 300 steps."""
+    rng = np.random.default_rng(3)
+    a11, a12 = W.diagonal_bands(512, 512, rng, n_bands=16)
+    v0 = W.fourier_celerity(512, 512, rng, kmax=2)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 300, every=100, limiter="minmod", cfl=0.45,
+                                v0_field=v0)
+    _assert_report(rep, 300)
+
+
+def test_c3_full_size_short(fdm, oracle):
+    """C3 at its full size (4096^2) for 4 steps, full grid."""
+    a11, a12, v0 = W.c3_bands(4096, seed=3)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 4, every=2, limiter="minmod", cfl=0.45, v0_field=v0)
+    assert dt <= 0.45 / np.abs(v0).max()
+    _assert_report(rep, 4)
+
+
+# ------------------------------------------------------------ edge cases
+
+ODD = [(1, 1), (1, 9), (9, 1), (3, 5), (65, 3), (1000, 3), (7, 130), (61, 61), (121, 67), (60, 4), (120, 2)]
+
+
+@pytest.mark.parametrize("nx,ny", ODD)
+@pytest.mark.parametrize("limiter", ["superbee", "mc"])
+def test_odd_sizes(fdm, oracle, nx, ny, limiter):
+    rng = np.random.default_rng(nx * 1000 + ny)
+    phi = rng.normal(size=(ny, nx))
+    phi = phi + np.roll(phi, 1, 0) + np.roll(phi, 1, 1)
+    a11, a12 = (x.astype(np.float32) for x in densities(phi, 1.0, 1.0))
+    v0 = W.fourier_celerity(nx, ny, rng, kmax=1)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 20, every=10, limiter=limiter, cfl=0.4, v0_field=v0)
+    _assert_report(rep, 20)
+
+
+def test_zero_and_immobile(fdm):
+    z = np.zeros((33, 70), np.float32)
+    dt, out = gpu_run(z, z, 10, limiter="superbee", v0=-1.0)
+    assert not np.any(out[-1][1]) and not np.any(out[-1][2])
+    rng = np.random.default_rng(1)
+    a11, a12 = (x.astype(np.float32) for x in densities(rng.normal(size=(33, 70)), 1.0, 1.0))
+    dt, out = gpu_run(a11, a12, 10, limiter="mc", v0_field=np.zeros((33, 70), np.float32))
+    assert np.array_equal(out[-1][1], a11) and np.array_equal(out[-1][2], a12)
+
+
+# ---------------------------------------------------- GPU self-consistency
+
+def test_translation_invariance_bitwise(fdm):
+    """Integer periodic shifts commute with the step, bit for bit (catches
+    tile-edge and halo mistakes: the strip/chunk boundaries move)."""
+    rng = np.random.default_rng(5)
+    ny, nx = 130, 150
+    a11, a12 = (x.astype(np.float32) for x in densities(rng.normal(size=(ny, nx)), 1.0, 1.0))
+    _, base = gpu_run(a11, a12, 25, limiter="superbee", v0=-0.7, options={"tile_rows": 8})
+    for sh in [(1, 0), (0, 1), (37, 61), (129, 149)]:
+        _, moved = gpu_run(np.roll(a11, sh, (0, 1)), np.roll(a12, sh, (0, 1)), 25, limiter="superbee",
+                           v0=-0.7, options={"tile_rows": 8})
+        assert np.array_equal(moved[-1][1], np.roll(base[-1][1], sh, (0, 1)))
+        assert np.array_equal(moved[-1][2], np.roll(base[-1][2], sh, (0, 1)))
+
+
+def test_tile_rows_bitwise(fdm):
+    a11, a12 = W.ring(200, 170, R=40.0, sigma=4.0)
+    outs = [gpu_run(a11, a12, 30, limiter="mc", v0=-1.0, options={"tile_rows": r})[1][-1] for r in (1, 3, 16, 64)]
+    for o in outs[1:]:
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+
+
+def test_deterministic(fdm):
+    a11, a12, v0 = W.c3_bands(512, seed=7)
+    r1 = gpu_run(a11, a12, 50, limiter="minmod", cfl=0.45, v0_field=v0)[1][-1]
+    r2 = gpu_run(a11, a12, 50, limiter="minmod", cfl=0.45, v0_field=v0)[1][-1]
+    assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
+
+
+# -------------------------------------------------------------- reductions
+
+def test_stats_match_oracle(fdm, oracle):
+    from paper_1911_03225_amd import fdm as F
+    a11, a12, v0 = W.c3_bands(1024, seed=11)
+    t11, t12 = to_dev(a11), to_dev(a12)
+    vf = to_dev(v0)
+    ctx = F.fdm_transport_init(F.desc(1024, 1024, limiter="minmod", cfl=0.45, v0_field=vf), keep=[vf])
+    for k in range(3):
+        s = F.fdm_transport_stats(ctx, t11, t12)[0]
+        o = oracle.stats(t11.cpu().numpy(), t12.cpu().numpy())
+        assert s["sum11"] == pytest.approx(o["sum11"], rel=1e-14, abs=1e-9)
+        assert s["sum12"] == pytest.approx(o["sum12"], rel=1e-14, abs=1e-9)
+        assert s["sum_abs"] == pytest.approx(o["sum_abs"], rel=1e-14)
+        assert s["max_norm"] == o["max_norm"]
+        assert s["nonfinite"] == 0
+        F.fdm_transport_step(ctx, t11, t12, 40)
+    F.fdm_destroy(ctx)
+
+
+# ------------------------------------------------- batched, graphs, errors
+
+def _mixed_instances():
+    rng = np.random.default_rng(21)
+    cases = []
+    for (nx, ny), lim, kind in [((64, 64), "minmod", "field"), ((130, 70), "superbee", "uniform"),
+                                ((1, 33), "mc", "uniform"), ((256, 128), "minmod", "field"),
+                                ((61, 59), "superbee", "uniform"), ((200, 200), "mc", "uniform")]:
+        a11, a12 = W.ring(nx, ny, R=max(2.0, min(nx, ny) / 4), sigma=2.0)
+        if kind == "field":
+            a11, a12 = W.diagonal_bands(nx, ny, rng, n_bands=4)
+        v0f = W.fourier_celerity(nx, ny, rng, kmax=1) if kind == "field" else None
+        cases.append(dict(nx=nx, ny=ny, a11=a11, a12=a12, limiter=lim, v0_field=v0f,
+                          v0=float(rng.choice([-1.0, 1.0]))))
+    return cases
+
+
+def _run_many(F, cases, schedule, n_steps, use_run=False):
+    import torch
+    keep, descs, t11, t12 = [], [], [], []
+    for c in cases:
+        vf = to_dev(c["v0_field"]) if c["v0_field"] is not None else None
+        if vf is not None:
+            keep.append(vf)
+        descs.append(F.desc(c["nx"], c["ny"], limiter=c["limiter"], cfl=0.4, v0=c["v0"], v0_field=vf))
+        t11.append(to_dev(c["a11"]))
+        t12.append(to_dev(c["a12"]))
+    ctx = F.fdm_transport_init(descs, options={"schedule": schedule}, keep=keep)
+    if use_run:
+        F.fdm_run(ctx, t11, t12, n_steps, 10)
+    else:
+        F.fdm_transport_step(ctx, t11, t12, n_steps)
+    torch.cuda.synchronize()
+    dts = [F.fdm_transport_dt(ctx, i) for i in range(len(cases))]
+    F.fdm_destroy(ctx)
+    return dts, [(x.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)) for x, y in zip(t11, t12)]
+
+
+def test_batched_equals_plain_bitwise_and_oracle(fdm, oracle):
+    from paper_1911_03225_amd import fdm as F
+    cases = _mixed_instances()
+    dts, plain = _run_many(F, cases, "plain", 40)
+    dts2, batched = _run_many(F, cases, "batched", 40)
+    assert dts == dts2
+    for c, p, b, dt in zip(cases, plain, batched, dts):
+        assert np.array_equal(p[0], b[0]) and np.array_equal(p[1], b[1])
+        P = oracle_problem(oracle, c["nx"], c["ny"], dt, limiter=c["limiter"], v0=c["v0"], v0_field=c["v0_field"])
+        o11, o12 = oracle.run(P, c["a11"], c["a12"], 40)
+        assert rel_l1(b[0], b[1], o11, o12, c["a11"], c["a12"]) <= tolerance(40)
+
+
+def test_run_graph_equals_step(fdm):
+    from paper_1911_03225_amd import fdm as F
+    cases = _mixed_instances()
+    _, stepped = _run_many(F, cases, "batched", 45)
+    _, ran = _run_many(F, cases, "batched", 45, use_run=True)
+    for a, b in zip(stepped, ran):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_run_history(fdm, oracle):
+    from paper_1911_03225_amd import fdm as F
+    a11, a12 = W.ring(128, 128, R=30.0, sigma=3.0)
+    t11, t12 = to_dev(a11), to_dev(a12)
+    ctx = F.fdm_transport_init(F.desc(128, 128, limiter="mc", cfl=0.4, v0=-1.0))
+    hist = F.fdm_run(ctx, t11, t12, 55, 20)
+    assert len(hist) == 3 and [h[0]["step"] for h in hist] == [20, 40, 55]
+    dt = F.fdm_transport_dt(ctx)
+    assert hist[-1][0]["t"] == pytest.approx(55 * dt)
+    o = oracle.stats(t11.cpu().numpy(), t12.cpu().numpy())
+    assert hist[-1][0]["sum_abs"] == pytest.approx(o["sum_abs"], rel=1e-14)
+    F.fdm_destroy(ctx)
+
+
+def test_error_paths(fdm):
+    from paper_1911_03225_amd import fdm as F
+    a11, a12 = W.ring(64, 64, R=16.0, sigma=2.0)
+    # a fixed dt above the Courant-number-1 bound
+    with pytest.raises(F.FdmError) as e:
+        F.fdm_transport_init(F.desc(64, 64, v0=-2.0, dt=0.6))
+    assert e.value.status == F.FDM_ERR_CFL
+    # a non-finite celerity field
+    bad = np.ones((64, 64), np.float32)
+    bad[3, 5] = np.nan
+    with pytest.raises(F.FdmError) as e:
+        F.fdm_transport_init(F.desc(64, 64, v0_field=to_dev(bad)))
+    assert e.value.status == F.FDM_ERR_INVALID_ARG
+    # NaN in the densities is reported by the diagnostics
+    ctx = F.fdm_transport_init(F.desc(64, 64, v0=-1.0))
+    t11, t12 = to_dev(a11), to_dev(a12)
+    t12[10, 10] = float("nan")
+    with pytest.raises(F.FdmError) as e:
+        F.fdm_transport_stats(ctx, t11, t12)
+    assert e.value.status == F.FDM_ERR_NONFINITE
+    s = F.fdm_transport_stats(ctx, t11, t12, allow_nonfinite=True)[0]
+    assert s["nonfinite"] == 1
+    # aliasing arrays
+    with pytest.raises(F.FdmError) as e:
+        F.fdm_transport_step(ctx, t11, t11, 1)
+    assert e.value.status == F.FDM_ERR_INVALID_ARG
+    F.fdm_destroy(ctx)
