@@ -107,12 +107,22 @@ typedef enum fdm_schedule {
     FDM_SCHEDULE_PLAIN = 2     /* one launch per stage per instance            */
 } fdm_schedule;
 
+/* Arithmetic of the stage kernels.  The densities are float32 in memory
+ * either way.  FP32 (default): slopes, numerical Hamiltonian and update in
+ * float32.  FP64: the same steps in float64 registers, results rounded once
+ * to float32 when stored; for shock-dominated runs where float32
+ * cancellations at the foot of a front meet the discontinuity of the speed
+ * v0 p/|p| at p = 0. */
+typedef enum fdm_precision {
+    FDM_PRECISION_FP32 = 0,
+    FDM_PRECISION_FP64 = 1
+} fdm_precision;
+
 typedef struct fdm_options {
     int32_t schedule;        /* fdm_schedule                                    */
     int32_t tile_rows;       /* rows per wave tile; 0 picks a default           */
-    int32_t fused;           /* time_order 2: 0 auto, 1 fused step kernel,
-                                -1 two stage kernels                            */
-    int32_t reserved;
+    int32_t fused;           /* reserved, must be 0                             */
+    int32_t precision;       /* fdm_precision                                   */
 } fdm_options;
 
 /* Per-instance diagnostics (FP64, deterministic: fixed-order compensated

@@ -26,6 +26,7 @@ struct fdm_ctx {
     int32_t n = 0;
     int32_t time_order = 2;
     int32_t schedule = FDM_SCHEDULE_AUTO;
+    int32_t precision = FDM_PRECISION_FP32;
     bool batched = false;
     std::vector<fdm_transport_desc> desc;
     std::vector<InstDev> inst;              // host copies of the device views
@@ -179,9 +180,10 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
         }
         for (int m = 0; m < nm; ++m) {
             if (c->batched) {
-                FDM_HIP(c, fdm::launch_stage_batched(c->d_inst, c->d_tile_inst, c->total_tiles, modes[m], s));
+                FDM_HIP(c, fdm::launch_stage_batched(c->d_inst, c->d_tile_inst, c->total_tiles, modes[m],
+                                                     c->precision, s));
             } else {
-                for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_stage(c->inst[i], modes[m], s));
+                for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_stage(c->inst[i], modes[m], c->precision, s));
             }
         }
     }
@@ -250,6 +252,9 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     if (opt.schedule < FDM_SCHEDULE_AUTO || opt.schedule > FDM_SCHEDULE_PLAIN)
         return fail(nullptr, FDM_ERR_INVALID_ARG, "unknown schedule");
     if (opt.tile_rows < 0) return fail(nullptr, FDM_ERR_INVALID_ARG, "tile_rows must be >= 0");
+    if (opt.fused != 0) return fail(nullptr, FDM_ERR_INVALID_ARG, "fused is reserved and must be 0");
+    if (opt.precision != FDM_PRECISION_FP32 && opt.precision != FDM_PRECISION_FP64)
+        return fail(nullptr, FDM_ERR_INVALID_ARG, "unknown precision");
     int32_t order = -1;
     for (int i = 0; i < n_instances; ++i) {
         const std::string m = check_desc(descs[i]);
@@ -267,6 +272,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     c->n = n_instances;
     c->time_order = order;
     c->schedule = opt.schedule;
+    c->precision = opt.precision;
     c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN;
     c->desc.assign(descs, descs + n_instances);
     c->inst.resize(n_instances);
@@ -345,9 +351,12 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         I.v0 = (float)d.v0;
         I.V1 = (float)d.V[0];
         I.V2 = (float)d.V[1];
-        I.cx = (float)((double)dt / d.dx);
-        I.cy = (float)((double)dt / d.dy);
-        I.theta = d.limiter == FDM_LIMITER_MINMOD ? 1.0f : d.limiter == FDM_LIMITER_MC ? 2.0f : (float)d.theta;
+        I.cxd = (double)dt / d.dx;
+        I.cyd = (double)dt / d.dy;
+        I.thetad = d.limiter == FDM_LIMITER_MINMOD ? 1.0 : d.limiter == FDM_LIMITER_MC ? 2.0 : d.theta;
+        I.cx = (float)I.cxd;
+        I.cy = (float)I.cyd;
+        I.theta = (float)I.thetad;
         I.limiter = d.limiter;
         I.vkind = d.velocity;
         I.rows = pick_rows(d, opt.tile_rows);

@@ -26,6 +26,9 @@ enum : int { VK_LAW = 0, VK_PRESCRIBED = 1 };
 //   MODE_HEUN2 : a = a/2 + (w + dt L(w))/2       (second Heun stage, in place)
 enum : int { MODE_FWD = 0, MODE_BWD = 1, MODE_HEUN2 = 2 };
 
+// Arithmetic of the stage kernels (the state is float32 either way).
+enum : int { PREC_FP32 = 0, PREC_FP64 = 1 };
+
 // Device view of one transport instance.
 struct InstDev {
     float *a11, *a12;        // state, caller-owned
@@ -40,6 +43,7 @@ struct InstDev {
     int32_t strips, chunks;  // tiles along x and y
     int32_t pad;
     int64_t tile_begin;      // first global tile of this instance (batched)
+    double cxd, cyd, thetad; // the same coefficients for FP64 arithmetic
 };
 
 // Per-block partial of the diagnostics reduction (compensated sums).
@@ -49,9 +53,9 @@ struct StatsPartial {
 
 constexpr int kStatsBlocks = 128;   // fixed => deterministic reduction order
 
-hipError_t launch_stage(const InstDev &I, int mode, hipStream_t s);
+hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s);
 hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst,
-                                int64_t total_tiles, int mode, hipStream_t s);
+                                int64_t total_tiles, int mode, int precision, hipStream_t s);
 hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s);
 hipError_t launch_stats(const float *a11, const float *a12, int64_t n,
                         StatsPartial *d_partials, double *d_out, hipStream_t s);

@@ -45,6 +45,58 @@ __device__ __forceinline__ float from_right(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
+__device__ __forceinline__ double from_left(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double from_right(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// ------------------------------------------------------- arithmetic types
+//
+// float: the default FP32 arithmetic.  double: FP64 register arithmetic on
+// the same float32 state (loads widened, results rounded once when stored);
+// FP64 VALU issues at the non-packed FP32 rate on gfx950.
+
+__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ float vabs(float a) { return fabsf(a); }
+__device__ __forceinline__ float vsign(float m, float s) { return copysignf(m, s); }
+__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ double vabs(double a) { return fabs(a); }
+__device__ __forceinline__ double vsign(double m, double s) { return copysign(m, s); }
+
+template <typename R> struct Arith;
+
+template <> struct Arith<float> {
+    static constexpr float tiny = 1.17549435e-38f;   // FLT_MIN
+    static __device__ __forceinline__ float rsq(float r) { return __builtin_amdgcn_rsqf(r); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+};
+
+template <> struct Arith<double> {
+    static constexpr double tiny = 2.2250738585072014e-308;   // DBL_MIN
+    // hardware estimates refined by one Newton step
+    static __device__ __forceinline__ double rsq(double r)
+    {
+        const double y = __builtin_amdgcn_rsq(r);
+        return y * (1.5 - 0.5 * r * y * y);
+    }
+    static __device__ __forceinline__ double rcp(double x)
+    {
+        const double y = __builtin_amdgcn_rcp(x);
+        return y * (2.0 - x * y);
+    }
+};
+
 // ---------------------------------------------------------------- Step 1
 
 // Limiter kinds compiled separately: the minmod family shares one body with
@@ -61,61 +113,64 @@ __host__ __device__ constexpr int limiter_kind(int lim)
 // theta-minmod: minmod(theta*D+, (w+ - w-)/2, theta*D-), written as
 // max(min3, 0) + min(max3, 0): the minimum if all three are positive, the
 // maximum if all are negative, else zero.  Odd in w, exactly.
-template <int LK>
-__device__ __forceinline__ float limited_slope(float wm, float w0, float wp, float theta)
+template <int LK, typename R>
+__device__ __forceinline__ R limited_slope(R wm, R w0, R wp, R theta)
 {
     if constexpr (LK == LK_NONE) {
-        return 0.0f;
+        return R(0);
     } else if constexpr (LK == LK_SUPERBEE) {
-        const float dm = w0 - wm, dp = wp - w0;
-        const float adm = fabsf(dm), adp = fabsf(dp);
-        const float mag = fmaxf(fminf(2.0f * adm, adp), fminf(adm, 2.0f * adp));
-        return (dm * dp > 0.0f) ? copysignf(mag, dp) : 0.0f;
+        const R dm = w0 - wm, dp = wp - w0;
+        const R adm = vabs(dm), adp = vabs(dp);
+        const R mag = vmax(vmin(R(2) * adm, adp), vmin(adm, R(2) * adp));
+        return (dm * dp > R(0)) ? vsign(mag, dp) : R(0);
     } else {
-        const float dm = w0 - wm, dp = wp - w0;
-        const float a = theta * dp, b = 0.5f * (wp - wm), c = theta * dm;
-        const float lo = fminf(fminf(a, b), c), hi = fmaxf(fmaxf(a, b), c);
-        return fmaxf(lo, 0.0f) + fminf(hi, 0.0f);
+        const R dm = w0 - wm, dp = wp - w0;
+        const R a = theta * dp, b = R(0.5) * (wp - wm), c = theta * dm;
+        const R lo = vmin(vmin(a, b), c), hi = vmax(vmax(a, b), c);
+        return vmax(lo, R(0)) + vmin(hi, R(0));
     }
 }
 
 // ---------------------------------------------------------- Steps 2 to 4
 
-template <int VK>
-__device__ __forceinline__ float numerical_hamiltonian(float pxm, float pxp, float pym, float pyp,
-                                                       float v0, float V1, float V2)
+template <int VK, typename R>
+__device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R v0, R V1, R V2)
 {
     if constexpr (VK == VK_PRESCRIBED) {
         // H = V.p: the central-upwind weights reduce to pure upwinding.
-        const float px = V1 > 0.0f ? pxm : pxp;
-        const float py = V2 > 0.0f ? pym : pyp;
+        const R px = V1 > R(0) ? pxm : pxp;
+        const R py = V2 > R(0) ? pym : pyp;
         return V1 * px + V2 * py;
     } else {
         // H = v0 |p| at the four corners (s,t) in {-,+}^2; dH/dp = v0 p/|p|,
-        // taken as 0 at p = 0.
-        const float xm2 = pxm * pxm, xp2 = pxp * pxp, ym2 = pym * pym, yp2 = pyp * pyp;
-        const float r00 = xm2 + ym2, r01 = xm2 + yp2, r10 = xp2 + ym2, r11 = xp2 + yp2;
-        const float g00 = r00 > 0.0f ? v0 * __builtin_amdgcn_rsqf(r00) : 0.0f;
-        const float g01 = r01 > 0.0f ? v0 * __builtin_amdgcn_rsqf(r01) : 0.0f;
-        const float g10 = r10 > 0.0f ? v0 * __builtin_amdgcn_rsqf(r10) : 0.0f;
-        const float g11 = r11 > 0.0f ? v0 * __builtin_amdgcn_rsqf(r11) : 0.0f;
-        const float H00 = r00 * g00, H01 = r01 * g01, H10 = r10 * g10, H11 = r11 * g11;
-        const float hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
-        const float hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
+        // taken as 0 at p = 0.  v_rsq/v_rcp read a subnormal input as zero
+        // (and return +inf), so |p|^2 or a+ - a- below the smallest normal
+        // number count as zero: the terms dropped are below 1e-19 |v0|
+        // (float) or 1e-154 |v0| (double).
+        constexpr R kTiny = Arith<R>::tiny;
+        const R xm2 = pxm * pxm, xp2 = pxp * pxp, ym2 = pym * pym, yp2 = pyp * pyp;
+        const R r00 = xm2 + ym2, r01 = xm2 + yp2, r10 = xp2 + ym2, r11 = xp2 + yp2;
+        const R g00 = r00 >= kTiny ? v0 * Arith<R>::rsq(r00) : R(0);
+        const R g01 = r01 >= kTiny ? v0 * Arith<R>::rsq(r01) : R(0);
+        const R g10 = r10 >= kTiny ? v0 * Arith<R>::rsq(r10) : R(0);
+        const R g11 = r11 >= kTiny ? v0 * Arith<R>::rsq(r11) : R(0);
+        const R H00 = r00 * g00, H01 = r01 * g01, H10 = r10 * g10, H11 = r11 * g11;
+        const R hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
+        const R hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
         // Step 2: one-sided local speeds over the four combinations
-        const float ap = fmaxf(fmaxf(fmaxf(hx00, hx01), fmaxf(hx10, hx11)), 0.0f);
-        const float am = fminf(fminf(fminf(hx00, hx01), fminf(hx10, hx11)), 0.0f);
-        const float bp = fmaxf(fmaxf(fmaxf(hy00, hy01), fmaxf(hy10, hy11)), 0.0f);
-        const float bm = fminf(fminf(fminf(hy00, hy01), fminf(hy10, hy11)), 0.0f);
+        const R ap = vmax(vmax(vmax(hx00, hx01), vmax(hx10, hx11)), R(0));
+        const R am = vmin(vmin(vmin(hx00, hx01), vmin(hx10, hx11)), R(0));
+        const R bp = vmax(vmax(vmax(hy00, hy01), vmax(hy10, hy11)), R(0));
+        const R bm = vmin(vmin(vmin(hy00, hy01), vmin(hy10, hy11)), R(0));
         // Steps 3-4 (dt -> 0): projection weights; 1/2 each and no viscosity
         // when nothing moves along that axis
-        const float da = ap - am, db = bp - bm;
-        const bool mx = da > 0.0f, my = db > 0.0f;
-        const float ia = mx ? __builtin_amdgcn_rcpf(da) : 0.0f;
-        const float ib = my ? __builtin_amdgcn_rcpf(db) : 0.0f;
-        const float wxm = mx ? ap * ia : 0.5f, wxp = mx ? -am * ia : 0.5f;
-        const float wym = my ? bp * ib : 0.5f, wyp = my ? -bm * ib : 0.5f;
-        const float visc_x = ap * am * ia, visc_y = bp * bm * ib;
+        const R da = ap - am, db = bp - bm;
+        const bool mx = da >= kTiny, my = db >= kTiny;
+        const R ia = mx ? Arith<R>::rcp(da) : R(0);
+        const R ib = my ? Arith<R>::rcp(db) : R(0);
+        const R wxm = mx ? ap * ia : R(0.5), wxp = mx ? -am * ia : R(0.5);
+        const R wym = my ? bp * ib : R(0.5), wyp = my ? -bm * ib : R(0.5);
+        const R visc_x = ap * am * ia, visc_y = bp * bm * ib;
         return wxm * (wym * H00 + wyp * H01) + wxp * (wym * H10 + wyp * H11)
              + visc_x * (pxp - pxm) + visc_y * (pyp - pym);
     }
@@ -128,16 +183,20 @@ __device__ __forceinline__ int next_row(int k, int ny)
 }
 
 // One wave: columns strip*60 .. strip*60+59 (lanes 2..61), rows
-// chunk*rows .. +rows-1, of one stage.
-template <int LK, int VK, bool FIELD, int MODE>
+// chunk*rows .. +rows-1, of one stage, in arithmetic type R.
+template <typename R, int LK, int VK, bool FIELD, int MODE>
 __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
 {
+    constexpr bool kF64 = sizeof(R) == 8;
     const int nx = I.nx, ny = I.ny;
     const float *__restrict__ s12 = MODE == MODE_FWD ? I.a12 : I.w12;
     const float *__restrict__ s11 = MODE == MODE_FWD ? I.a11 : I.w11;
     float *__restrict__ d12 = MODE == MODE_FWD ? I.w12 : I.a12;
     float *__restrict__ d11 = MODE == MODE_FWD ? I.w11 : I.a11;
-    const float theta = I.theta, cx = I.cx, cy = I.cy;
+    const R theta = kF64 ? R(I.thetad) : R(I.theta);
+    const R cx = kF64 ? R(I.cxd) : R(I.cx);
+    const R cy = kF64 ? R(I.cyd) : R(I.cy);
+    const R V1 = R(I.V1), V2 = R(I.V2);
 
     const int gcol = strip * kStrip - kHalo + lane;
     int col = gcol % nx;
@@ -149,47 +208,47 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     // alpha_11 = -w_y on y-edges; the window holds rows k-2, k-1, k.
     int k = (k0 - 2) % ny;
     if (k < 0) k += ny;
-    const float ym2 = s11[k * nx + col];
+    const R ym2 = R(s11[k * nx + col]);
     k = next_row(k, ny);
-    float ym1 = s11[k * nx + col];
+    R ym1 = R(s11[k * nx + col]);
     k = next_row(k, ny);
-    float y0 = s11[k * nx + col];
-    float sm1 = limited_slope<LK>(ym2, ym1, y0, theta);   // slope at edge k-1/2
-    float hprev = 0.0f;
+    R y0 = R(s11[k * nx + col]);
+    R sm1 = limited_slope<LK>(ym2, ym1, y0, theta);   // slope at edge k-1/2
+    R hprev = R(0);
     int kprev = k;
 
     for (int it = 0; it <= nrows; ++it) {
         const int kn = next_row(k, ny);
         const int rk = k * nx + col;
-        const float wx = s12[rk];
-        const float yp1 = s11[kn * nx + col];
-        float v0 = I.v0;
-        if constexpr (FIELD) v0 = I.v0f[rk];
+        const R wx = R(s12[rk]);
+        const R yp1 = R(s11[kn * nx + col]);
+        R v0 = R(I.v0);
+        if constexpr (FIELD) v0 = R(I.v0f[rk]);
 
         // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
-        const float s0 = limited_slope<LK>(ym1, y0, yp1, theta);
-        const float pyp = -(y0 - 0.5f * s0);
-        const float pym = -(ym1 + 0.5f * sm1);
+        const R s0 = limited_slope<LK>(ym1, y0, yp1, theta);
+        const R pyp = -(y0 - R(0.5) * s0);
+        const R pym = -(ym1 + R(0.5) * sm1);
         // Steps 1-2 along x (alpha_12 = w_x), neighbours from adjacent lanes
-        const float wl = from_left(wx), wr = from_right(wx);
-        const float sx = limited_slope<LK>(wl, wx, wr, theta);
-        const float pxp = wx - 0.5f * sx;
-        const float pxm = from_left(wx + 0.5f * sx);
+        const R wl = from_left(wx), wr = from_right(wx);
+        const R sx = limited_slope<LK>(wl, wx, wr, theta);
+        const R pxp = wx - R(0.5) * sx;
+        const R pxm = from_left(wx + R(0.5) * sx);
         // Steps 2-4
-        const float h = numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, I.V1, I.V2);
-        const float hr = from_right(h);
+        const R h = numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
+        const R hr = from_right(h);
 
         if (out_col) {
             if (it < nrows) {            // x-edge (j+1/2, k)
-                float nv = wx - cx * (hr - h);
-                if constexpr (MODE == MODE_HEUN2) nv = 0.5f * d12[rk] + 0.5f * nv;
-                d12[rk] = nv;
+                R nv = wx - cx * (hr - h);
+                if constexpr (MODE == MODE_HEUN2) nv = R(0.5) * R(d12[rk]) + R(0.5) * nv;
+                d12[rk] = float(nv);
             }
             if (it > 0) {                // y-edge (j, k-1/2)
                 const int rp = kprev * nx + col;
-                float nv = ym1 + cy * (h - hprev);
-                if constexpr (MODE == MODE_HEUN2) nv = 0.5f * d11[rp] + 0.5f * nv;
-                d11[rp] = nv;
+                R nv = ym1 + cy * (h - hprev);
+                if constexpr (MODE == MODE_HEUN2) nv = R(0.5) * R(d11[rp]) + R(0.5) * nv;
+                d11[rp] = float(nv);
             }
         }
         hprev = h;
@@ -212,19 +271,19 @@ __device__ __forceinline__ int64_t xcd_tile(int blocks_per_xcd)
     return logical * kWavesPerBlock + wave;
 }
 
-template <int LK, int VK, bool FIELD, int MODE>
+template <typename R, int LK, int VK, bool FIELD, int MODE>
 __global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd)
 {
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
     const int t = (int)tile;
-    run_tile<LK, VK, FIELD, MODE>(I, t / I.chunks, t % I.chunks, threadIdx.x & 63);
+    run_tile<R, LK, VK, FIELD, MODE>(I, t / I.chunks, t % I.chunks, threadIdx.x & 63);
 }
 
 // Batched: one launch for every tile of every instance; tile_inst maps a
 // global tile to its instance.  Limiter, Hamiltonian and field presence are
 // per instance and uniform over a wave.
-template <int MODE>
+template <typename R, int MODE>
 __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__restrict__ insts,
                                                                const int32_t *__restrict__ tile_inst,
                                                                int64_t total_tiles, int blocks_per_xcd)
@@ -237,17 +296,17 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__
     const int lane = threadIdx.x & 63;
     const int lk = limiter_kind(I.limiter);
     if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) run_tile<LK_NONE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<LK_SUPERBEE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
-        else run_tile<LK_THETA, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
+        if (lk == LK_NONE) run_tile<R, LK_NONE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
+        else if (lk == LK_SUPERBEE) run_tile<R, LK_SUPERBEE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
+        else run_tile<R, LK_THETA, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
     } else if (I.v0f != nullptr) {
-        if (lk == LK_NONE) run_tile<LK_NONE, VK_LAW, true, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<LK_SUPERBEE, VK_LAW, true, MODE>(I, strip, chunk, lane);
-        else run_tile<LK_THETA, VK_LAW, true, MODE>(I, strip, chunk, lane);
+        if (lk == LK_NONE) run_tile<R, LK_NONE, VK_LAW, true, MODE>(I, strip, chunk, lane);
+        else if (lk == LK_SUPERBEE) run_tile<R, LK_SUPERBEE, VK_LAW, true, MODE>(I, strip, chunk, lane);
+        else run_tile<R, LK_THETA, VK_LAW, true, MODE>(I, strip, chunk, lane);
     } else {
-        if (lk == LK_NONE) run_tile<LK_NONE, VK_LAW, false, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<LK_SUPERBEE, VK_LAW, false, MODE>(I, strip, chunk, lane);
-        else run_tile<LK_THETA, VK_LAW, false, MODE>(I, strip, chunk, lane);
+        if (lk == LK_NONE) run_tile<R, LK_NONE, VK_LAW, false, MODE>(I, strip, chunk, lane);
+        else if (lk == LK_SUPERBEE) run_tile<R, LK_SUPERBEE, VK_LAW, false, MODE>(I, strip, chunk, lane);
+        else run_tile<R, LK_THETA, VK_LAW, false, MODE>(I, strip, chunk, lane);
     }
 }
 
@@ -387,7 +446,7 @@ __global__ __launch_bounds__(256) void copy_kernel(float *__restrict__ dst, cons
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-template <int LK, int VK, bool FIELD>
+template <typename R, int LK, int VK, bool FIELD>
 hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
 {
     const int64_t tiles = (int64_t)I.strips * I.chunks;
@@ -395,47 +454,61 @@ hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
     if (mode == MODE_FWD)
-        hipLaunchKernelGGL((stage_kernel<LK, VK, FIELD, MODE_FWD>), grid, block, 0, s, I, tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel<R, LK, VK, FIELD, MODE_FWD>), grid, block, 0, s, I, tiles, per_xcd);
     else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel<LK, VK, FIELD, MODE_BWD>), grid, block, 0, s, I, tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel<R, LK, VK, FIELD, MODE_BWD>), grid, block, 0, s, I, tiles, per_xcd);
     else
-        hipLaunchKernelGGL((stage_kernel<LK, VK, FIELD, MODE_HEUN2>), grid, block, 0, s, I, tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel<R, LK, VK, FIELD, MODE_HEUN2>), grid, block, 0, s, I, tiles, per_xcd);
     return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_stage(const InstDev &I, int mode, hipStream_t s)
+template <typename R>
+hipError_t launch_stage_r(const InstDev &I, int mode, hipStream_t s)
 {
     const int lk = limiter_kind(I.limiter);
     if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) return launch_stage_t<LK_NONE, VK_PRESCRIBED, false>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<LK_SUPERBEE, VK_PRESCRIBED, false>(I, mode, s);
-        return launch_stage_t<LK_THETA, VK_PRESCRIBED, false>(I, mode, s);
+        if (lk == LK_NONE) return launch_stage_t<R, LK_NONE, VK_PRESCRIBED, false>(I, mode, s);
+        if (lk == LK_SUPERBEE) return launch_stage_t<R, LK_SUPERBEE, VK_PRESCRIBED, false>(I, mode, s);
+        return launch_stage_t<R, LK_THETA, VK_PRESCRIBED, false>(I, mode, s);
     }
     if (I.v0f != nullptr) {
-        if (lk == LK_NONE) return launch_stage_t<LK_NONE, VK_LAW, true>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<LK_SUPERBEE, VK_LAW, true>(I, mode, s);
-        return launch_stage_t<LK_THETA, VK_LAW, true>(I, mode, s);
+        if (lk == LK_NONE) return launch_stage_t<R, LK_NONE, VK_LAW, true>(I, mode, s);
+        if (lk == LK_SUPERBEE) return launch_stage_t<R, LK_SUPERBEE, VK_LAW, true>(I, mode, s);
+        return launch_stage_t<R, LK_THETA, VK_LAW, true>(I, mode, s);
     }
-    if (lk == LK_NONE) return launch_stage_t<LK_NONE, VK_LAW, false>(I, mode, s);
-    if (lk == LK_SUPERBEE) return launch_stage_t<LK_SUPERBEE, VK_LAW, false>(I, mode, s);
-    return launch_stage_t<LK_THETA, VK_LAW, false>(I, mode, s);
+    if (lk == LK_NONE) return launch_stage_t<R, LK_NONE, VK_LAW, false>(I, mode, s);
+    if (lk == LK_SUPERBEE) return launch_stage_t<R, LK_SUPERBEE, VK_LAW, false>(I, mode, s);
+    return launch_stage_t<R, LK_THETA, VK_LAW, false>(I, mode, s);
 }
 
-hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
-                                int mode, hipStream_t s)
+template <typename R>
+hipError_t launch_batched_r(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles, int mode,
+                            hipStream_t s)
 {
     const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
     if (mode == MODE_FWD)
-        hipLaunchKernelGGL(stage_kernel_batched<MODE_FWD>, grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel_batched<R, MODE_FWD>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
     else if (mode == MODE_BWD)
-        hipLaunchKernelGGL(stage_kernel_batched<MODE_BWD>, grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel_batched<R, MODE_BWD>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
     else
-        hipLaunchKernelGGL(stage_kernel_batched<MODE_HEUN2>, grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel_batched<R, MODE_HEUN2>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s)
+{
+    return precision == PREC_FP64 ? launch_stage_r<double>(I, mode, s) : launch_stage_r<float>(I, mode, s);
+}
+
+hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
+                                int mode, int precision, hipStream_t s)
+{
+    return precision == PREC_FP64 ? launch_batched_r<double>(d_inst, d_tile_inst, total_tiles, mode, s)
+                                  : launch_batched_r<float>(d_inst, d_tile_inst, total_tiles, mode, s);
 }
 
 hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s)

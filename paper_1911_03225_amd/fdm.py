@@ -23,6 +23,7 @@ FDM_ERR_CFL, FDM_ERR_NONFINITE, FDM_ERR_UNSUPPORTED = 4, 5, 6
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2, "theta": 3, "superbee": 4}
 VELOCITIES = {"law": 0, "prescribed": 1}
 SCHEDULES = {"auto": 0, "batched": 1, "plain": 2}
+PRECISIONS = {"fp32": 0, "fp64": 1}
 
 
 class fdm_transport_desc(ctypes.Structure):
@@ -38,7 +39,7 @@ class fdm_transport_desc(ctypes.Structure):
 
 class fdm_options(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("fused", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fused", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class fdm_stats(ctypes.Structure):
@@ -196,6 +197,8 @@ def fdm_transport_init(descs, options=None, stream=None, keep=()):
                 if isinstance(options.get("schedule", "auto"), str) else int(options["schedule"])
             o.tile_rows = int(options.get("tile_rows", 0))
             o.fused = int(options.get("fused", 0))
+            prec = options.get("precision", "fp32")
+            o.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
             options = o
         opt = ctypes.byref(options)
     h = ctypes.c_void_p()

@@ -119,3 +119,10 @@ def test_valid_descriptor_without_gpu_fails_cleanly(fdm):
     with pytest.raises(fdm.FdmError) as e:
         fdm.fdm_transport_init(fdm.desc(16, 16))
     assert e.value.status == fdm.FDM_ERR_DEVICE
+
+
+def test_invalid_options_rejected(fdm):
+    for opts in ({"precision": 7}, {"schedule": 9}, {"tile_rows": -1}, {"fused": 1}):
+        with pytest.raises(fdm.FdmError) as e:
+            fdm.fdm_transport_init(fdm.desc(16, 16), options=opts)
+        assert e.value.status == fdm.FDM_ERR_INVALID_ARG
