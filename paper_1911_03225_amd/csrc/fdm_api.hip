@@ -107,13 +107,24 @@ float round_down_float(double x)
     return f;
 }
 
-// Rows per wave tile: enough waves to fill 256 CUs several times over.
+// Rows per wave tile.  Each tile recomputes one extra row of Hhat and
+// reloads four rows of alpha_11, so long tiles are cheaper per row; but the
+// grid should still offer at least one wave per wave slot of the chip
+// (256 CUs x 4 SIMDs x 8 waves) so every SIMD has latency to hide.  Take the
+// longest tile in {8, 16, 32} meeting that, else 8 (measured on MI355X:
+// 2048^2 runs fastest with 8, 4 and 16 are 9% and 2% slower).
 int pick_rows(const fdm_transport_desc &d, int requested)
 {
     if (requested > 0) return std::min(requested, d.ny);
     const int64_t strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
-    int rows = 32;
-    while (rows > 4 && strips * ((d.ny + rows - 1) / rows) < 16384) rows >>= 1;
+    const int64_t slots = 256 * 4 * 8;
+    int rows = 8;
+    for (int r : {32, 16}) {
+        if (strips * ((d.ny + r - 1) / r) >= slots) {
+            rows = r;
+            break;
+        }
+    }
     return std::min(rows, d.ny);
 }
 

@@ -51,7 +51,7 @@ struct StatsPartial {
     double s11, c11, s12, c12, sab, cab, maxn, nonfinite;
 };
 
-constexpr int kStatsBlocks = 128;   // fixed => deterministic reduction order
+constexpr int kStatsBlocks = 512;   // fixed => deterministic reduction order
 
 hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s);
 hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst,

@@ -142,18 +142,18 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         const R py = V2 > R(0) ? pym : pyp;
         return V1 * px + V2 * py;
     } else {
-        // H = v0 |p| at the four corners (s,t) in {-,+}^2; dH/dp = v0 p/|p|,
-        // taken as 0 at p = 0.  v_rsq/v_rcp read a subnormal input as zero
-        // (and return +inf), so |p|^2 or a+ - a- below the smallest normal
-        // number count as zero: the terms dropped are below 1e-19 |v0|
-        // (float) or 1e-154 |v0| (double).
+        // H = v0 |p| at the four corners (s,t) in {-,+}^2, dH/dp = v0 p/|p|.
+        // |p|^2 is clamped below at the smallest normal number before the
+        // reciprocal square root (v_rsq reads a subnormal as zero): p = 0
+        // still gives H = 0 and speed 0, and gradients below 1e-19 (float)
+        // move with speed v0 p / 1e-19 instead of a full-speed direction.
         constexpr R kTiny = Arith<R>::tiny;
         const R xm2 = pxm * pxm, xp2 = pxp * pxp, ym2 = pym * pym, yp2 = pyp * pyp;
         const R r00 = xm2 + ym2, r01 = xm2 + yp2, r10 = xp2 + ym2, r11 = xp2 + yp2;
-        const R g00 = r00 >= kTiny ? v0 * Arith<R>::rsq(r00) : R(0);
-        const R g01 = r01 >= kTiny ? v0 * Arith<R>::rsq(r01) : R(0);
-        const R g10 = r10 >= kTiny ? v0 * Arith<R>::rsq(r10) : R(0);
-        const R g11 = r11 >= kTiny ? v0 * Arith<R>::rsq(r11) : R(0);
+        const R g00 = v0 * Arith<R>::rsq(vmax(r00, kTiny));
+        const R g01 = v0 * Arith<R>::rsq(vmax(r01, kTiny));
+        const R g10 = v0 * Arith<R>::rsq(vmax(r10, kTiny));
+        const R g11 = v0 * Arith<R>::rsq(vmax(r11, kTiny));
         const R H00 = r00 * g00, H01 = r01 * g01, H10 = r10 * g10, H11 = r11 * g11;
         const R hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
         const R hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
@@ -163,7 +163,12 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         const R bp = vmax(vmax(vmax(hy00, hy01), vmax(hy10, hy11)), R(0));
         const R bm = vmin(vmin(vmin(hy00, hy01), vmin(hy10, hy11)), R(0));
         // Steps 3-4 (dt -> 0): projection weights; 1/2 each and no viscosity
-        // when nothing moves along that axis
+        // when nothing moves along that axis.  The sum keeps the order of
+        // the definition (weighted corner values, then the two viscosity
+        // terms): rewriting it, e.g. with w_+ = 1 - w_-, lets FMA
+        // contraction turn exact cancellations between equal corner values
+        // into product rounding errors, which the kink of |p| at p = 0
+        // then amplifies.
         const R da = ap - am, db = bp - bm;
         const bool mx = da >= kTiny, my = db >= kTiny;
         const R ia = mx ? Arith<R>::rcp(da) : R(0);
@@ -182,17 +187,36 @@ __device__ __forceinline__ int next_row(int k, int ny)
     return k == ny ? 0 : k;
 }
 
+// Row `row` of a field, at this lane's byte offset: the row address is
+// wave-uniform (scalar registers), the offset a 32-bit lane value.
+__device__ __forceinline__ const float *row_ptr(const float *base, int row, int nx)
+{
+    return base + (size_t)row * (size_t)nx;
+}
+
+__device__ __forceinline__ float at(const float *row, uint32_t off)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(row) + off);
+}
+
+__device__ __forceinline__ void put(float *row, uint32_t off, float v)
+{
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(row) + off) = v;
+}
+
 // One wave: columns strip*60 .. strip*60+59 (lanes 2..61), rows
-// chunk*rows .. +rows-1, of one stage, in arithmetic type R.
+// chunk*rows .. +rows-1, of one stage, in arithmetic type R.  Loads run one
+// row ahead of the arithmetic so their latency overlaps the previous row.
 template <typename R, int LK, int VK, bool FIELD, int MODE>
 __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
 {
     constexpr bool kF64 = sizeof(R) == 8;
+    constexpr bool kBase = MODE == MODE_HEUN2;
     const int nx = I.nx, ny = I.ny;
-    const float *__restrict__ s12 = MODE == MODE_FWD ? I.a12 : I.w12;
-    const float *__restrict__ s11 = MODE == MODE_FWD ? I.a11 : I.w11;
-    float *__restrict__ d12 = MODE == MODE_FWD ? I.w12 : I.a12;
-    float *__restrict__ d11 = MODE == MODE_FWD ? I.w11 : I.a11;
+    const float *s12 = MODE == MODE_FWD ? I.a12 : I.w12;
+    const float *s11 = MODE == MODE_FWD ? I.a11 : I.w11;
+    float *d12 = MODE == MODE_FWD ? I.w12 : I.a12;
+    float *d11 = MODE == MODE_FWD ? I.w11 : I.a11;
     const R theta = kF64 ? R(I.thetad) : R(I.theta);
     const R cx = kF64 ? R(I.cxd) : R(I.cx);
     const R cy = kF64 ? R(I.cyd) : R(I.cy);
@@ -201,6 +225,7 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     const int gcol = strip * kStrip - kHalo + lane;
     int col = gcol % nx;
     if (col < 0) col += nx;
+    const uint32_t off = (uint32_t)col * 4u;
     const bool out_col = lane >= kHalo && lane < kHalo + kStrip && gcol < nx;
     const int k0 = chunk * I.rows;
     const int nrows = min(I.rows, ny - k0);
@@ -208,22 +233,38 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     // alpha_11 = -w_y on y-edges; the window holds rows k-2, k-1, k.
     int k = (k0 - 2) % ny;
     if (k < 0) k += ny;
-    const R ym2 = R(s11[k * nx + col]);
+    const R ym2 = R(at(row_ptr(s11, k, nx), off));
     k = next_row(k, ny);
-    R ym1 = R(s11[k * nx + col]);
+    R ym1 = R(at(row_ptr(s11, k, nx), off));
+    const int kprev0 = k;
     k = next_row(k, ny);
-    R y0 = R(s11[k * nx + col]);
+    R y0 = R(at(row_ptr(s11, k, nx), off));
     R sm1 = limited_slope<LK>(ym2, ym1, y0, theta);   // slope at edge k-1/2
     R hprev = R(0);
-    int kprev = k;
+    int kprev = kprev0;
+
+    // first row's operands
+    int kn = next_row(k, ny);
+    float f_wx = at(row_ptr(s12, k, nx), off);
+    float f_yp1 = at(row_ptr(s11, kn, nx), off);
+    float f_v0 = FIELD ? at(row_ptr(I.v0f, k, nx), off) : 0.0f;
+    float f_b12 = kBase ? at(row_ptr(d12, k, nx), off) : 0.0f;
+    float f_b11 = kBase ? at(row_ptr(d11, kprev, nx), off) : 0.0f;
 
     for (int it = 0; it <= nrows; ++it) {
-        const int kn = next_row(k, ny);
-        const int rk = k * nx + col;
-        const R wx = R(s12[rk]);
-        const R yp1 = R(s11[kn * nx + col]);
-        R v0 = R(I.v0);
-        if constexpr (FIELD) v0 = R(I.v0f[rk]);
+        const R wx = R(f_wx), yp1 = R(f_yp1);
+        const R v0 = FIELD ? R(f_v0) : R(I.v0);
+        const R b12 = R(f_b12), b11 = R(f_b11);
+        const int knn = next_row(kn, ny);
+        if (it < nrows) {   // operands of the next row (wave-uniform branch)
+            f_wx = at(row_ptr(s12, kn, nx), off);
+            f_yp1 = at(row_ptr(s11, knn, nx), off);
+            if constexpr (FIELD) f_v0 = at(row_ptr(I.v0f, kn, nx), off);
+            if constexpr (kBase) {
+                f_b12 = at(row_ptr(d12, kn, nx), off);
+                f_b11 = at(row_ptr(d11, k, nx), off);
+            }
+        }
 
         // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
         const R s0 = limited_slope<LK>(ym1, y0, yp1, theta);
@@ -241,19 +282,19 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         if (out_col) {
             if (it < nrows) {            // x-edge (j+1/2, k)
                 R nv = wx - cx * (hr - h);
-                if constexpr (MODE == MODE_HEUN2) nv = R(0.5) * R(d12[rk]) + R(0.5) * nv;
-                d12[rk] = float(nv);
+                if constexpr (kBase) nv = R(0.5) * b12 + R(0.5) * nv;
+                put(const_cast<float *>(row_ptr(d12, k, nx)), off, float(nv));
             }
             if (it > 0) {                // y-edge (j, k-1/2)
-                const int rp = kprev * nx + col;
                 R nv = ym1 + cy * (h - hprev);
-                if constexpr (MODE == MODE_HEUN2) nv = R(0.5) * R(d11[rp]) + R(0.5) * nv;
-                d11[rp] = float(nv);
+                if constexpr (kBase) nv = R(0.5) * b11 + R(0.5) * nv;
+                put(const_cast<float *>(row_ptr(d11, kprev, nx)), off, float(nv));
             }
         }
         hprev = h;
         kprev = k;
         k = kn;
+        kn = knn;
         ym1 = y0;
         y0 = yp1;
         sm1 = s0;
