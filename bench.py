@@ -39,6 +39,74 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _make_instance(inst):
+    a11, a12, v0 = inst.make()
+    return a11, a12, v0
+
+
+def batched_vs_plain(fdm, workloads, K, log):
+    """The batched workload (384 instances, ~90M nodes): one K-step chunk as
+    one graph of batched launches against one launch per instance per stage."""
+    import concurrent.futures as cf
+    import numpy as np
+    import torch
+
+    insts = workloads.c5_instances()
+    t0 = time.perf_counter()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    import multiprocessing as mp
+    # fresh worker interpreters: this process already holds a GPU context
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        arrays = list(ex.map(_make_instance, insts, chunksize=4))
+    log("bench[c5]: generated %d instances in %.1f s" % (len(insts), time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    base11 = [torch.from_numpy(a[0]).to(dev) for a in arrays]
+    base12 = [torch.from_numpy(a[1]).to(dev) for a in arrays]
+    fields = [torch.from_numpy(a[2]).to(dev) if a[2] is not None else None for a in arrays]
+    descs = [fdm.desc(i.nx, i.ny, limiter=i.limiter, cfl=0.4, v0=i.v0, v0_field=f) for i, f in zip(insts, fields)]
+    nodes = sum(i.nx * i.ny for i in insts)
+    stream = torch.cuda.current_stream()
+    out = {}
+    finals = {}
+    for sched in ("batched", "plain"):
+        s11 = [b.clone() for b in base11]
+        s12 = [b.clone() for b in base12]
+        ctx = fdm.fdm_transport_init(descs, options={"schedule": sched}, stream=stream, keep=fields)
+        if sched == "batched":
+            fdm.fdm_run(ctx, s11, s12, K, K, history=False)      # capture + warm
+        else:
+            fdm.fdm_transport_step(ctx, s11, s12, 2)
+        torch.cuda.synchronize()
+        # restart from the same inputs for the timed chunk
+        for a, b in zip(s11, base11):
+            a.copy_(b)
+        for a, b in zip(s12, base12):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if sched == "batched":
+            fdm.fdm_run(ctx, s11, s12, K, K, history=False)
+        else:
+            fdm.fdm_transport_step(ctx, s11, s12, K)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt_s = e0.elapsed_time(e1) / 1000.0
+        stats = fdm.fdm_transport_stats(ctx, s11, s12, allow_nonfinite=True)
+        fdm.fdm_destroy(ctx)
+        out[sched] = {"seconds": round(dt_s, 4), "cell_updates_per_s": round(nodes * K / dt_s, 1),
+                      "nonfinite_instances": sum(1 for st in stats if st["nonfinite"])}
+        finals[sched] = (s11, s12)
+        log("bench[c5]: %s %d steps in %.3f s (%.3e cell-updates/s)" % (sched, K, dt_s, nodes * K / dt_s))
+    same = all(torch.equal(a, b) for a, b in zip(finals["batched"][0], finals["plain"][0])) and \
+        all(torch.equal(a, b) for a, b in zip(finals["batched"][1], finals["plain"][1]))
+    return {"instances": len(insts), "nodes": nodes, "chunk_steps": K,
+            "batched": out["batched"], "plain": out["plain"],
+            "speedup": round(out["plain"]["seconds"] / out["batched"]["seconds"], 3),
+            "bitwise_equal": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +119,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-c5", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--c5-steps", type=int, default=500)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -112,6 +182,10 @@ def main():
     final = hist[-1][0]
     fdm.fdm_destroy(ctx)
 
+    c5 = None
+    if not args.no_c5:
+        c5 = batched_vs_plain(fdm, workloads, args.c5_steps, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -143,6 +217,7 @@ def main():
         "hbm_frac_algorithmic": round(value * BYTES_PER_CELL_STEP / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_vs_plain": c5,
         "final_stats": {"step": final["step"], "sum_abs": final["sum_abs"], "max_norm": final["max_norm"],
                         "drift11": final["drift11"], "drift12": final["drift12"]},
     }
