@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
-BYTES_PER_CELL_STEP = 16        # read + write alpha_11 and alpha_12 once (float32)
+BYTES_PER_CELL_STEP = 16        # read + write alpha_11 and alpha_12 once (float32; 32 for float64)
 # One VALU lane-operation per lane per cycle (packed FP32 is not used):
 # 256 CUs x 64 lanes x 2.4 GHz.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64_arith", "fp64"])
     ap.add_argument("--no-c5", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--c5-steps", type=int, default=500)
     args = ap.parse_args()
@@ -138,8 +138,9 @@ def main():
     log("bench: generating %dx%d ring" % (n, n))
     a11, a12 = workloads.ring(n, n, R=R, sigma=sigma)
     dev = torch.device("cuda:0")
-    t11 = torch.from_numpy(a11).to(dev)
-    t12 = torch.from_numpy(a12).to(dev)
+    state = torch.float64 if args.precision == "fp64" else torch.float32
+    t11 = torch.from_numpy(a11).to(dev).to(state)
+    t12 = torch.from_numpy(a12).to(dev).to(state)
     stream = torch.cuda.current_stream()
     options = {"tile_rows": args.tile_rows, "precision": args.precision}
     ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter=args.limiter, cfl=cfl, v0=-1.0), options=options,
@@ -208,7 +209,7 @@ def main():
     out = {
         "metric": "transport cell-updates/s", "value": round(value, 1), "unit": "cell-updates/s",
         "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64 arithmetic, f32 state",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64_arith": "f64 arithmetic, f32 state", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "single loop %dx%d (ring R=%g sigma=%g), LAW v0=-1, %s, Heun, CFL %g"
                                % (n, n, R, sigma, args.limiter, cfl),

@@ -11,7 +11,8 @@
  *
  * Grid and layout.  nx by ny pixel nodes x_j = j dx, y_k = k dy (sec. 3.2.3),
  * periodic in both directions; nx, ny >= 1 (ny = 1 is a 1-D problem along x).
- * Arrays are row-major, index k * nx + j, x fastest, float32, device memory:
+ * Arrays are row-major, index k * nx + j, x fastest, device memory, float32
+ * (double with FDM_PRECISION_FP64, see fdm_options):
  *   alpha12[k*nx + j]  alpha_12 = d1 U^p_13 on the x-edge ((j+1/2) dx, k dy);
  *   alpha11[k*nx + j]  alpha_11 = -d2 U^p_13 on the y-edge (j dx, (k+1/2) dy).
  * These are the differences of U^p_13 between neighbouring nodes, so the
@@ -107,15 +108,22 @@ typedef enum fdm_schedule {
     FDM_SCHEDULE_PLAIN = 2     /* one launch per stage per instance            */
 } fdm_schedule;
 
-/* Arithmetic of the stage kernels.  The densities are float32 in memory
- * either way.  FP32 (default): slopes, numerical Hamiltonian and update in
- * float32.  FP64: the same steps in float64 registers, results rounded once
- * to float32 when stored; for shock-dominated runs where float32
- * cancellations at the foot of a front meet the discontinuity of the speed
- * v0 p/|p| at p = 0. */
+/* Precision of the stage kernels.
+ * FP32 (default): float32 densities, slopes, numerical Hamiltonian and update
+ *   in float32.
+ * FP64_ARITH: float32 densities; the same steps in float64 registers, results
+ *   rounded once to float32 when stored.  Removes the float32 cancellations at
+ *   the foot of a front that the discontinuity of the speed v0 p/|p| at p = 0
+ *   amplifies (shock-dominated runs).
+ * FP64: float64 densities (the arrays passed to step/stats/run are double)
+ *   and float64 arithmetic.  Rounding the state to float32 after every stage
+ *   is itself a perturbation the scheme amplifies over hundreds of steps, so
+ *   long runs agree with a float64 evaluation of the scheme to 1e-5 only with
+ *   float64 state.  A v0 field stays float32 in every mode. */
 typedef enum fdm_precision {
     FDM_PRECISION_FP32 = 0,
-    FDM_PRECISION_FP64 = 1
+    FDM_PRECISION_FP64_ARITH = 1,
+    FDM_PRECISION_FP64 = 2
 } fdm_precision;
 
 typedef struct fdm_options {
@@ -152,17 +160,18 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
                               fdm_ctx **out);
 
 /* Enqueue n_steps >= 0 time steps of every instance.  alpha11[i], alpha12[i]
- * are the device arrays of instance i (see layout above); they are read and
- * written in place.  Asynchronous: returns after enqueueing. */
-fdm_status fdm_transport_step(fdm_ctx *ctx, float *const *alpha11,
-                              float *const *alpha12, int32_t n_steps);
+ * are the device arrays of instance i (see layout above; float, or double
+ * with FDM_PRECISION_FP64); they are read and written in place.
+ * Asynchronous: returns after enqueueing. */
+fdm_status fdm_transport_step(fdm_ctx *ctx, void *const *alpha11,
+                              void *const *alpha12, int32_t n_steps);
 
 /* Diagnostics of every instance's current state into out[0..n_instances-1]
  * (sums, norms, non-finite count; see fdm_stats).  Synchronizes the stream.
  * Returns FDM_ERR_NONFINITE (after filling out) if any instance holds a NaN
  * or Inf. */
-fdm_status fdm_transport_stats(fdm_ctx *ctx, float *const *alpha11,
-                               float *const *alpha12, fdm_stats *out);
+fdm_status fdm_transport_stats(fdm_ctx *ctx, void *const *alpha11,
+                               void *const *alpha12, fdm_stats *out);
 
 /* Static problem (sec. 3.1.2): layer-averaged shear stress tau_13 (sec.
  * 3.2.1) of a homogeneous isotropic cell for given layer densities. */
@@ -197,8 +206,8 @@ typedef struct fdm_loading {
  * within a chunk).  history may be NULL.  Synchronizes the stream once per
  * chunk when history is given, once at the end otherwise.
  * loading != NULL (coupled) returns FDM_ERR_UNSUPPORTED in this build. */
-fdm_status fdm_run(fdm_ctx *ctx, const fdm_loading *loading, float *const *alpha11,
-                   float *const *alpha12, int32_t n_steps, int32_t chunk,
+fdm_status fdm_run(fdm_ctx *ctx, const fdm_loading *loading, void *const *alpha11,
+                   void *const *alpha12, int32_t n_steps, int32_t chunk,
                    fdm_stats *history);
 
 /* The float32 time step of instance i (after init), or -1 on a bad argument. */

@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdm.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("fdm_kernels.hip", "fdm_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in
+           ("fdm_kernels.hip", "fdm_stage_f32.hip", "fdm_stage_f64.hip", "fdm_api.hip")]
 ARCH = "gfx950"
 
 

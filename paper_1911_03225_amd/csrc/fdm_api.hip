@@ -31,7 +31,7 @@ struct fdm_ctx {
     std::vector<fdm_transport_desc> desc;
     std::vector<InstDev> inst;              // host copies of the device views
     std::vector<float> dt;                  // float32 step per instance
-    float *workspace = nullptr;             // all stage buffers
+    void *workspace = nullptr;              // all stage buffers
     InstDev *d_inst = nullptr;              // batched: device table
     InstDev *h_inst_pinned = nullptr;       // staging for table uploads
     int32_t *d_tile_inst = nullptr;         // batched: tile -> instance
@@ -47,7 +47,7 @@ struct fdm_ctx {
     // graph cache for fdm_run
     hipGraphExec_t graph = nullptr;
     int32_t graph_steps = 0;
-    std::vector<float *> graph_a11, graph_a12;
+    std::vector<void *> graph_a11, graph_a12;
     bool sticky = false;
     std::string err;
 };
@@ -144,7 +144,7 @@ void release(fdm_ctx *c)
     delete c;
 }
 
-fdm_status check_ptrs(fdm_ctx *c, float *const *a11, float *const *a12)
+fdm_status check_ptrs(fdm_ctx *c, void *const *a11, void *const *a12)
 {
     if (!a11 || !a12) return fail(c, FDM_ERR_INVALID_ARG, "alpha11/alpha12 pointer arrays must not be NULL");
     for (int i = 0; i < c->n; ++i) {
@@ -156,7 +156,7 @@ fdm_status check_ptrs(fdm_ctx *c, float *const *a11, float *const *a12)
 
 // Point the device views at this call's arrays; re-upload the batched table
 // when they changed.
-fdm_status bind(fdm_ctx *c, float *const *a11, float *const *a12)
+fdm_status bind(fdm_ctx *c, void *const *a11, void *const *a12)
 {
     bool changed = !c->table_valid;
     for (int i = 0; i < c->n; ++i) {
@@ -203,18 +203,18 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
     if (c->time_order == 1 && (n_steps & 1)) {
         for (int i = 0; i < c->n; ++i) {
             const int64_t n = (int64_t)c->inst[i].nx * c->inst[i].ny;
-            FDM_HIP(c, fdm::launch_copy(c->inst[i].a11, c->inst[i].w11, n, s));
-            FDM_HIP(c, fdm::launch_copy(c->inst[i].a12, c->inst[i].w12, n, s));
+            FDM_HIP(c, fdm::launch_copy(c->inst[i].a11, c->inst[i].w11, n, c->precision, s));
+            FDM_HIP(c, fdm::launch_copy(c->inst[i].a12, c->inst[i].w12, n, c->precision, s));
         }
     }
     return FDM_OK;
 }
 
-fdm_status compute_stats(fdm_ctx *c, float *const *a11, float *const *a12, fdm_stats *out)
+fdm_status compute_stats(fdm_ctx *c, void *const *a11, void *const *a12, fdm_stats *out)
 {
     for (int i = 0; i < c->n; ++i) {
         const int64_t n = (int64_t)c->inst[i].nx * c->inst[i].ny;
-        FDM_HIP(c, fdm::launch_stats(a11[i], a12[i], n, c->d_partials, c->d_stats + 5 * i, c->stream));
+        FDM_HIP(c, fdm::launch_stats(a11[i], a12[i], n, c->precision, c->d_partials, c->d_stats + 5 * i, c->stream));
     }
     FDM_HIP(c, hipMemcpyAsync(c->h_stats, c->d_stats, sizeof(double) * 5 * c->n, hipMemcpyDeviceToHost,
                               c->stream));
@@ -264,7 +264,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         return fail(nullptr, FDM_ERR_INVALID_ARG, "unknown schedule");
     if (opt.tile_rows < 0) return fail(nullptr, FDM_ERR_INVALID_ARG, "tile_rows must be >= 0");
     if (opt.fused != 0) return fail(nullptr, FDM_ERR_INVALID_ARG, "fused is reserved and must be 0");
-    if (opt.precision != FDM_PRECISION_FP32 && opt.precision != FDM_PRECISION_FP64)
+    if (opt.precision < FDM_PRECISION_FP32 || opt.precision > FDM_PRECISION_FP64)
         return fail(nullptr, FDM_ERR_INVALID_ARG, "unknown precision");
     int32_t order = -1;
     for (int i = 0; i < n_instances; ++i) {
@@ -307,7 +307,8 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     // workspace: one stage buffer (both components) per instance
     int64_t total = 0;
     for (int i = 0; i < n_instances; ++i) total += 2 * (int64_t)descs[i].nx * descs[i].ny;
-    INIT_HIP(hipMalloc((void **)&c->workspace, sizeof(float) * total));
+    const size_t elem = opt.precision == FDM_PRECISION_FP64 ? sizeof(double) : sizeof(float);
+    INIT_HIP(hipMalloc((void **)&c->workspace, elem * total));
     INIT_HIP(hipMalloc((void **)&c->d_partials, sizeof(fdm::StatsPartial) * fdm::kStatsBlocks));
     INIT_HIP(hipMalloc((void **)&c->d_stats, sizeof(double) * 5 * n_instances));
     INIT_HIP(hipHostMalloc((void **)&c->h_stats, sizeof(double) * 5 * n_instances, hipHostMallocDefault));
@@ -353,8 +354,8 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
 
         InstDev &I = c->inst[i];
         std::memset(&I, 0, sizeof(I));
-        I.w11 = c->workspace + off;
-        I.w12 = c->workspace + off + n;
+        I.w11 = static_cast<char *>(c->workspace) + elem * off;
+        I.w12 = static_cast<char *>(c->workspace) + elem * (off + n);
         off += 2 * n;
         I.v0f = d.velocity == FDM_VELOCITY_LAW ? d.v0_field : nullptr;
         I.nx = d.nx;
@@ -362,6 +363,9 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         I.v0 = (float)d.v0;
         I.V1 = (float)d.V[0];
         I.V2 = (float)d.V[1];
+        I.dtd = (double)dt;
+        I.dxd = d.dx;
+        I.dyd = d.dy;
         I.cxd = (double)dt / d.dx;
         I.cyd = (double)dt / d.dy;
         I.thetad = d.limiter == FDM_LIMITER_MINMOD ? 1.0 : d.limiter == FDM_LIMITER_MC ? 2.0 : d.theta;
@@ -398,7 +402,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     return FDM_OK;
 }
 
-fdm_status fdm_transport_step(fdm_ctx *c, float *const *alpha11, float *const *alpha12, int32_t n_steps)
+fdm_status fdm_transport_step(fdm_ctx *c, void *const *alpha11, void *const *alpha12, int32_t n_steps)
 {
     if (!c) return FDM_ERR_INVALID_ARG;
     if (c->sticky) return FDM_ERR_DEVICE;
@@ -414,7 +418,7 @@ fdm_status fdm_transport_step(fdm_ctx *c, float *const *alpha11, float *const *a
     return FDM_OK;
 }
 
-fdm_status fdm_transport_stats(fdm_ctx *c, float *const *alpha11, float *const *alpha12, fdm_stats *out)
+fdm_status fdm_transport_stats(fdm_ctx *c, void *const *alpha11, void *const *alpha12, fdm_stats *out)
 {
     if (!c) return FDM_ERR_INVALID_ARG;
     if (c->sticky) return FDM_ERR_DEVICE;
@@ -436,7 +440,7 @@ fdm_status fdm_static_solve(const fdm_static_desc *desc, const float *alpha11, c
     return FDM_ERR_UNSUPPORTED;
 }
 
-fdm_status fdm_run(fdm_ctx *c, const fdm_loading *loading, float *const *alpha11, float *const *alpha12,
+fdm_status fdm_run(fdm_ctx *c, const fdm_loading *loading, void *const *alpha11, void *const *alpha12,
                    int32_t n_steps, int32_t chunk, fdm_stats *history)
 {
     if (!c) return FDM_ERR_INVALID_ARG;

@@ -26,13 +26,16 @@ enum : int { VK_LAW = 0, VK_PRESCRIBED = 1 };
 //   MODE_HEUN2 : a = a/2 + (w + dt L(w))/2       (second Heun stage, in place)
 enum : int { MODE_FWD = 0, MODE_BWD = 1, MODE_HEUN2 = 2 };
 
-// Arithmetic of the stage kernels (the state is float32 either way).
-enum : int { PREC_FP32 = 0, PREC_FP64 = 1 };
+// Precision modes (values of fdm_precision): arithmetic type / state type.
+//   PREC_FP32       float  / float
+//   PREC_FP64_ARITH double / float
+//   PREC_FP64       double / double
+enum : int { PREC_FP32 = 0, PREC_FP64_ARITH = 1, PREC_FP64 = 2 };
 
 // Device view of one transport instance.
 struct InstDev {
-    float *a11, *a12;        // state, caller-owned
-    float *w11, *w12;        // stage buffer, library-owned
+    void *a11, *a12;         // state, caller-owned (float, or double in PREC_FP64)
+    void *w11, *w12;         // stage buffer, library-owned, same type
     const float *v0f;        // node celerity field or nullptr
     int32_t nx, ny;
     float v0, V1, V2;        // uniform celerity / prescribed velocity
@@ -44,6 +47,7 @@ struct InstDev {
     int32_t pad;
     int64_t tile_begin;      // first global tile of this instance (batched)
     double cxd, cyd, thetad; // the same coefficients for FP64 arithmetic
+    double dtd, dxd, dyd;    // step and spacings (FP64 update in definition form)
 };
 
 // Per-block partial of the diagnostics reduction (compensated sums).
@@ -57,9 +61,9 @@ hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s
 hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst,
                                 int64_t total_tiles, int mode, int precision, hipStream_t s);
 hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s);
-hipError_t launch_stats(const float *a11, const float *a12, int64_t n,
+hipError_t launch_stats(const void *a11, const void *a12, int64_t n, int precision,
                         StatsPartial *d_partials, double *d_out, hipStream_t s);
-hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, int64_t n, int precision, hipStream_t s);
 
 constexpr int kAbsmaxBlocks = 256;
 

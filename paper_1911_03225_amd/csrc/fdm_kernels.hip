@@ -1,355 +1,31 @@
-// fdm_kernels.hip -- gfx950 kernels of the layer-case transport hot path.
-//
-// Scheme (Morin, Brenner & Suquet, arXiv:1911.03225, sec. 3.2.2-3.2.3): the
-// central-upwind Godunov-type update of U^p_13, carried out on its edge
-// differences, the in-plane Nye components alpha_12 (x-edges) and alpha_11
-// (y-edges).  Per node and stage:
-//   Step 1   limited slope of each component along its own axis (limited
-//            second difference of U^p_13, minmod family eq. 43-44, or
-//            superbee);
-//   Step 2   one-sided derivatives px-+, py-+ (eq. 46 per axis) and one-sided
-//            speeds a-+, b-+ over the four (+-,+-) combinations (eq. 53);
-//   Step 3-4 the dt -> 0 limit of the intermediate-point solve and projection
-//            (eq. 54-55), with the tensor-product (sign-corrected) weights:
-//            Hhat = sum w_s v_t H(px^s, py^t) + a+a-/(a+-a-) (px+ - px-)
-//                                             + b+b-/(b+-b-) (py+ - py-);
-//   update   alpha_12 -= dt/dx (Hhat_{j+1,k} - Hhat_{jk}),
-//            alpha_11 += dt/dy (Hhat_{j,k+1} - Hhat_{jk})  (eq. 57 form).
-//
-// Data movement (gfx950, wave64).  The stencil reaches two edges along each
-// axis.  A wave owns a strip of 60 output columns plus 2 halo lanes on each
-// side, one column per lane, and walks `rows` rows downwards:
-//   * y neighbours stay in registers (a sliding window of alpha_11 rows and
-//     the previous row's Hhat), so every row is read once per strip;
-//   * x neighbours come from adjacent lanes through DPP wave shifts;
-//   * no LDS, no barriers; every global access is a row of 64 consecutive
-//     floats.
-// Hhat is pure VALU work (4 rsq, 2 rcp per node); there is no contraction
-// for MFMA here.
+// fdm_kernels.hip -- reductions and helpers of the transport hot path, and
+// the precision dispatch of the stage kernels (fdm_stage_f32.hip,
+// fdm_stage_f64.hip).
 #include "fdm_internal.h"
 
 namespace fdm {
+
+hipError_t launch_stage_f32(const InstDev &I, int mode, hipStream_t s);
+hipError_t launch_stage_batched_f32(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
+                                    int mode, hipStream_t s);
+hipError_t launch_stage_f64(const InstDev &I, int mode, bool f64_state, hipStream_t s);
+hipError_t launch_stage_batched_f64(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
+                                    int mode, bool f64_state, hipStream_t s);
+
+hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s)
+{
+    if (precision == PREC_FP32) return launch_stage_f32(I, mode, s);
+    return launch_stage_f64(I, mode, precision == PREC_FP64, s);
+}
+
+hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
+                                int mode, int precision, hipStream_t s)
+{
+    if (precision == PREC_FP32) return launch_stage_batched_f32(d_inst, d_tile_inst, total_tiles, mode, s);
+    return launch_stage_batched_f64(d_inst, d_tile_inst, total_tiles, mode, precision == PREC_FP64, s);
+}
+
 namespace {
-
-// ---------------------------------------------------------------- lane moves
-
-// lane l receives lane l-1's value (lane 0 receives 0)
-__device__ __forceinline__ float from_left(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-
-// lane l receives lane l+1's value (lane 63 receives 0)
-__device__ __forceinline__ float from_right(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-
-__device__ __forceinline__ double from_left(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double from_right(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-// ------------------------------------------------------- arithmetic types
-//
-// float: the default FP32 arithmetic.  double: FP64 register arithmetic on
-// the same float32 state (loads widened, results rounded once when stored);
-// FP64 VALU issues at the non-packed FP32 rate on gfx950.
-
-__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
-__device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
-__device__ __forceinline__ float vabs(float a) { return fabsf(a); }
-__device__ __forceinline__ float vsign(float m, float s) { return copysignf(m, s); }
-__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
-__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
-__device__ __forceinline__ double vabs(double a) { return fabs(a); }
-__device__ __forceinline__ double vsign(double m, double s) { return copysign(m, s); }
-
-template <typename R> struct Arith;
-
-template <> struct Arith<float> {
-    static constexpr float tiny = 1.17549435e-38f;   // FLT_MIN
-    static __device__ __forceinline__ float rsq(float r) { return __builtin_amdgcn_rsqf(r); }
-    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-};
-
-template <> struct Arith<double> {
-    static constexpr double tiny = 2.2250738585072014e-308;   // DBL_MIN
-    // hardware estimates refined by one Newton step
-    static __device__ __forceinline__ double rsq(double r)
-    {
-        const double y = __builtin_amdgcn_rsq(r);
-        return y * (1.5 - 0.5 * r * y * y);
-    }
-    static __device__ __forceinline__ double rcp(double x)
-    {
-        const double y = __builtin_amdgcn_rcp(x);
-        return y * (2.0 - x * y);
-    }
-};
-
-// ---------------------------------------------------------------- Step 1
-
-// Limiter kinds compiled separately: the minmod family shares one body with
-// a runtime theta (1 for minmod, 2 for MC), so every launch form runs the
-// same instructions for a given limiter.
-enum : int { LK_NONE = 0, LK_THETA = 1, LK_SUPERBEE = 2 };
-
-__host__ __device__ constexpr int limiter_kind(int lim)
-{
-    return lim == LIM_NONE ? LK_NONE : (lim == LIM_SUPERBEE ? LK_SUPERBEE : LK_THETA);
-}
-
-// Limited slope at an edge from three consecutive values along its axis.
-// theta-minmod: minmod(theta*D+, (w+ - w-)/2, theta*D-), written as
-// max(min3, 0) + min(max3, 0): the minimum if all three are positive, the
-// maximum if all are negative, else zero.  Odd in w, exactly.
-template <int LK, typename R>
-__device__ __forceinline__ R limited_slope(R wm, R w0, R wp, R theta)
-{
-    if constexpr (LK == LK_NONE) {
-        return R(0);
-    } else if constexpr (LK == LK_SUPERBEE) {
-        const R dm = w0 - wm, dp = wp - w0;
-        const R adm = vabs(dm), adp = vabs(dp);
-        const R mag = vmax(vmin(R(2) * adm, adp), vmin(adm, R(2) * adp));
-        return (dm * dp > R(0)) ? vsign(mag, dp) : R(0);
-    } else {
-        const R dm = w0 - wm, dp = wp - w0;
-        const R a = theta * dp, b = R(0.5) * (wp - wm), c = theta * dm;
-        const R lo = vmin(vmin(a, b), c), hi = vmax(vmax(a, b), c);
-        return vmax(lo, R(0)) + vmin(hi, R(0));
-    }
-}
-
-// ---------------------------------------------------------- Steps 2 to 4
-
-template <int VK, typename R>
-__device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R v0, R V1, R V2)
-{
-    if constexpr (VK == VK_PRESCRIBED) {
-        // H = V.p: the central-upwind weights reduce to pure upwinding.
-        const R px = V1 > R(0) ? pxm : pxp;
-        const R py = V2 > R(0) ? pym : pyp;
-        return V1 * px + V2 * py;
-    } else {
-        // H = v0 |p| at the four corners (s,t) in {-,+}^2, dH/dp = v0 p/|p|.
-        // |p|^2 is clamped below at the smallest normal number before the
-        // reciprocal square root (v_rsq reads a subnormal as zero): p = 0
-        // still gives H = 0 and speed 0, and gradients below 1e-19 (float)
-        // move with speed v0 p / 1e-19 instead of a full-speed direction.
-        constexpr R kTiny = Arith<R>::tiny;
-        const R xm2 = pxm * pxm, xp2 = pxp * pxp, ym2 = pym * pym, yp2 = pyp * pyp;
-        const R r00 = xm2 + ym2, r01 = xm2 + yp2, r10 = xp2 + ym2, r11 = xp2 + yp2;
-        const R g00 = v0 * Arith<R>::rsq(vmax(r00, kTiny));
-        const R g01 = v0 * Arith<R>::rsq(vmax(r01, kTiny));
-        const R g10 = v0 * Arith<R>::rsq(vmax(r10, kTiny));
-        const R g11 = v0 * Arith<R>::rsq(vmax(r11, kTiny));
-        const R H00 = r00 * g00, H01 = r01 * g01, H10 = r10 * g10, H11 = r11 * g11;
-        const R hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
-        const R hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
-        // Step 2: one-sided local speeds over the four combinations
-        const R ap = vmax(vmax(vmax(hx00, hx01), vmax(hx10, hx11)), R(0));
-        const R am = vmin(vmin(vmin(hx00, hx01), vmin(hx10, hx11)), R(0));
-        const R bp = vmax(vmax(vmax(hy00, hy01), vmax(hy10, hy11)), R(0));
-        const R bm = vmin(vmin(vmin(hy00, hy01), vmin(hy10, hy11)), R(0));
-        // Steps 3-4 (dt -> 0): projection weights; 1/2 each and no viscosity
-        // when nothing moves along that axis.  The sum keeps the order of
-        // the definition (weighted corner values, then the two viscosity
-        // terms): rewriting it, e.g. with w_+ = 1 - w_-, lets FMA
-        // contraction turn exact cancellations between equal corner values
-        // into product rounding errors, which the kink of |p| at p = 0
-        // then amplifies.
-        const R da = ap - am, db = bp - bm;
-        const bool mx = da >= kTiny, my = db >= kTiny;
-        const R ia = mx ? Arith<R>::rcp(da) : R(0);
-        const R ib = my ? Arith<R>::rcp(db) : R(0);
-        const R wxm = mx ? ap * ia : R(0.5), wxp = mx ? -am * ia : R(0.5);
-        const R wym = my ? bp * ib : R(0.5), wyp = my ? -bm * ib : R(0.5);
-        const R visc_x = ap * am * ia, visc_y = bp * bm * ib;
-        return wxm * (wym * H00 + wyp * H01) + wxp * (wym * H10 + wyp * H11)
-             + visc_x * (pxp - pxm) + visc_y * (pyp - pym);
-    }
-}
-
-__device__ __forceinline__ int next_row(int k, int ny)
-{
-    k += 1;
-    return k == ny ? 0 : k;
-}
-
-// Row `row` of a field, at this lane's byte offset: the row address is
-// wave-uniform (scalar registers), the offset a 32-bit lane value.
-__device__ __forceinline__ const float *row_ptr(const float *base, int row, int nx)
-{
-    return base + (size_t)row * (size_t)nx;
-}
-
-__device__ __forceinline__ float at(const float *row, uint32_t off)
-{
-    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(row) + off);
-}
-
-__device__ __forceinline__ void put(float *row, uint32_t off, float v)
-{
-    *reinterpret_cast<float *>(reinterpret_cast<char *>(row) + off) = v;
-}
-
-// One wave: columns strip*60 .. strip*60+59 (lanes 2..61), rows
-// chunk*rows .. +rows-1, of one stage, in arithmetic type R.  Loads run one
-// row ahead of the arithmetic so their latency overlaps the previous row.
-template <typename R, int LK, int VK, bool FIELD, int MODE>
-__device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
-{
-    constexpr bool kF64 = sizeof(R) == 8;
-    constexpr bool kBase = MODE == MODE_HEUN2;
-    const int nx = I.nx, ny = I.ny;
-    const float *s12 = MODE == MODE_FWD ? I.a12 : I.w12;
-    const float *s11 = MODE == MODE_FWD ? I.a11 : I.w11;
-    float *d12 = MODE == MODE_FWD ? I.w12 : I.a12;
-    float *d11 = MODE == MODE_FWD ? I.w11 : I.a11;
-    const R theta = kF64 ? R(I.thetad) : R(I.theta);
-    const R cx = kF64 ? R(I.cxd) : R(I.cx);
-    const R cy = kF64 ? R(I.cyd) : R(I.cy);
-    const R V1 = R(I.V1), V2 = R(I.V2);
-
-    const int gcol = strip * kStrip - kHalo + lane;
-    int col = gcol % nx;
-    if (col < 0) col += nx;
-    const uint32_t off = (uint32_t)col * 4u;
-    const bool out_col = lane >= kHalo && lane < kHalo + kStrip && gcol < nx;
-    const int k0 = chunk * I.rows;
-    const int nrows = min(I.rows, ny - k0);
-
-    // alpha_11 = -w_y on y-edges; the window holds rows k-2, k-1, k.
-    int k = (k0 - 2) % ny;
-    if (k < 0) k += ny;
-    const R ym2 = R(at(row_ptr(s11, k, nx), off));
-    k = next_row(k, ny);
-    R ym1 = R(at(row_ptr(s11, k, nx), off));
-    const int kprev0 = k;
-    k = next_row(k, ny);
-    R y0 = R(at(row_ptr(s11, k, nx), off));
-    R sm1 = limited_slope<LK>(ym2, ym1, y0, theta);   // slope at edge k-1/2
-    R hprev = R(0);
-    int kprev = kprev0;
-
-    // first row's operands
-    int kn = next_row(k, ny);
-    float f_wx = at(row_ptr(s12, k, nx), off);
-    float f_yp1 = at(row_ptr(s11, kn, nx), off);
-    float f_v0 = FIELD ? at(row_ptr(I.v0f, k, nx), off) : 0.0f;
-    float f_b12 = kBase ? at(row_ptr(d12, k, nx), off) : 0.0f;
-    float f_b11 = kBase ? at(row_ptr(d11, kprev, nx), off) : 0.0f;
-
-    for (int it = 0; it <= nrows; ++it) {
-        const R wx = R(f_wx), yp1 = R(f_yp1);
-        const R v0 = FIELD ? R(f_v0) : R(I.v0);
-        const R b12 = R(f_b12), b11 = R(f_b11);
-        const int knn = next_row(kn, ny);
-        if (it < nrows) {   // operands of the next row (wave-uniform branch)
-            f_wx = at(row_ptr(s12, kn, nx), off);
-            f_yp1 = at(row_ptr(s11, knn, nx), off);
-            if constexpr (FIELD) f_v0 = at(row_ptr(I.v0f, kn, nx), off);
-            if constexpr (kBase) {
-                f_b12 = at(row_ptr(d12, kn, nx), off);
-                f_b11 = at(row_ptr(d11, k, nx), off);
-            }
-        }
-
-        // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
-        const R s0 = limited_slope<LK>(ym1, y0, yp1, theta);
-        const R pyp = -(y0 - R(0.5) * s0);
-        const R pym = -(ym1 + R(0.5) * sm1);
-        // Steps 1-2 along x (alpha_12 = w_x), neighbours from adjacent lanes
-        const R wl = from_left(wx), wr = from_right(wx);
-        const R sx = limited_slope<LK>(wl, wx, wr, theta);
-        const R pxp = wx - R(0.5) * sx;
-        const R pxm = from_left(wx + R(0.5) * sx);
-        // Steps 2-4
-        const R h = numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
-        const R hr = from_right(h);
-
-        if (out_col) {
-            if (it < nrows) {            // x-edge (j+1/2, k)
-                R nv = wx - cx * (hr - h);
-                if constexpr (kBase) nv = R(0.5) * b12 + R(0.5) * nv;
-                put(const_cast<float *>(row_ptr(d12, k, nx)), off, float(nv));
-            }
-            if (it > 0) {                // y-edge (j, k-1/2)
-                R nv = ym1 + cy * (h - hprev);
-                if constexpr (kBase) nv = R(0.5) * b11 + R(0.5) * nv;
-                put(const_cast<float *>(row_ptr(d11, kprev, nx)), off, float(nv));
-            }
-        }
-        hprev = h;
-        kprev = k;
-        k = kn;
-        kn = knn;
-        ym1 = y0;
-        y0 = yp1;
-        sm1 = s0;
-    }
-}
-
-// Hardware places block b on XCD b % 8.  Give each XCD a contiguous run of
-// tiles (vertically adjacent chunks of the same strips) so halo rows are
-// re-read from that XCD's L2.
-__device__ __forceinline__ int64_t xcd_tile(int blocks_per_xcd)
-{
-    const int b = blockIdx.x;
-    const int64_t logical = (int64_t)(b & 7) * blocks_per_xcd + (b >> 3);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    return logical * kWavesPerBlock + wave;
-}
-
-template <typename R, int LK, int VK, bool FIELD, int MODE>
-__global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd)
-{
-    const int64_t tile = xcd_tile(blocks_per_xcd);
-    if (tile >= total_tiles) return;
-    const int t = (int)tile;
-    run_tile<R, LK, VK, FIELD, MODE>(I, t / I.chunks, t % I.chunks, threadIdx.x & 63);
-}
-
-// Batched: one launch for every tile of every instance; tile_inst maps a
-// global tile to its instance.  Limiter, Hamiltonian and field presence are
-// per instance and uniform over a wave.
-template <typename R, int MODE>
-__global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__restrict__ insts,
-                                                               const int32_t *__restrict__ tile_inst,
-                                                               int64_t total_tiles, int blocks_per_xcd)
-{
-    const int64_t tile = xcd_tile(blocks_per_xcd);
-    if (tile >= total_tiles) return;
-    const InstDev I = insts[tile_inst[tile]];
-    const int local = (int)(tile - I.tile_begin);
-    const int strip = local / I.chunks, chunk = local % I.chunks;
-    const int lane = threadIdx.x & 63;
-    const int lk = limiter_kind(I.limiter);
-    if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) run_tile<R, LK_NONE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<R, LK_SUPERBEE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
-        else run_tile<R, LK_THETA, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
-    } else if (I.v0f != nullptr) {
-        if (lk == LK_NONE) run_tile<R, LK_NONE, VK_LAW, true, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<R, LK_SUPERBEE, VK_LAW, true, MODE>(I, strip, chunk, lane);
-        else run_tile<R, LK_THETA, VK_LAW, true, MODE>(I, strip, chunk, lane);
-    } else {
-        if (lk == LK_NONE) run_tile<R, LK_NONE, VK_LAW, false, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<R, LK_SUPERBEE, VK_LAW, false, MODE>(I, strip, chunk, lane);
-        else run_tile<R, LK_THETA, VK_LAW, false, MODE>(I, strip, chunk, lane);
-    }
-}
 
 // ---------------------------------------------------------------- reductions
 
@@ -413,15 +89,16 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double x)
     s = t;
 }
 
-__global__ __launch_bounds__(256) void stats_partial_kernel(const float *__restrict__ a11,
-                                                            const float *__restrict__ a12, int64_t n,
+template <typename S>
+__global__ __launch_bounds__(256) void stats_partial_kernel(const S *__restrict__ a11,
+                                                            const S *__restrict__ a12, int64_t n,
                                                             StatsPartial *__restrict__ out)
 {
     __shared__ StatsPartial lds[4];
     StatsPartial p = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const float x = a11[i], y = a12[i];
+        const S x = a11[i], y = a12[i];
         if (!isfinite(x) || !isfinite(y)) {
             p.nonfinite += 1.0;
             continue;
@@ -480,77 +157,14 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float *__restrict__ v
     }
 }
 
-__global__ __launch_bounds__(256) void copy_kernel(float *__restrict__ dst, const float *__restrict__ src,
-                                                   int64_t n)
+template <typename S>
+__global__ __launch_bounds__(256) void copy_kernel(S *__restrict__ dst, const S *__restrict__ src, int64_t n)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-template <typename R, int LK, int VK, bool FIELD>
-hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
-{
-    const int64_t tiles = (int64_t)I.strips * I.chunks;
-    const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int per_xcd = (int)((blocks + 7) / 8);
-    const dim3 grid(8 * per_xcd), block(kBlock);
-    if (mode == MODE_FWD)
-        hipLaunchKernelGGL((stage_kernel<R, LK, VK, FIELD, MODE_FWD>), grid, block, 0, s, I, tiles, per_xcd);
-    else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel<R, LK, VK, FIELD, MODE_BWD>), grid, block, 0, s, I, tiles, per_xcd);
-    else
-        hipLaunchKernelGGL((stage_kernel<R, LK, VK, FIELD, MODE_HEUN2>), grid, block, 0, s, I, tiles, per_xcd);
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t launch_stage_r(const InstDev &I, int mode, hipStream_t s)
-{
-    const int lk = limiter_kind(I.limiter);
-    if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) return launch_stage_t<R, LK_NONE, VK_PRESCRIBED, false>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, LK_SUPERBEE, VK_PRESCRIBED, false>(I, mode, s);
-        return launch_stage_t<R, LK_THETA, VK_PRESCRIBED, false>(I, mode, s);
-    }
-    if (I.v0f != nullptr) {
-        if (lk == LK_NONE) return launch_stage_t<R, LK_NONE, VK_LAW, true>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, LK_SUPERBEE, VK_LAW, true>(I, mode, s);
-        return launch_stage_t<R, LK_THETA, VK_LAW, true>(I, mode, s);
-    }
-    if (lk == LK_NONE) return launch_stage_t<R, LK_NONE, VK_LAW, false>(I, mode, s);
-    if (lk == LK_SUPERBEE) return launch_stage_t<R, LK_SUPERBEE, VK_LAW, false>(I, mode, s);
-    return launch_stage_t<R, LK_THETA, VK_LAW, false>(I, mode, s);
-}
-
-template <typename R>
-hipError_t launch_batched_r(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles, int mode,
-                            hipStream_t s)
-{
-    const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int per_xcd = (int)((blocks + 7) / 8);
-    const dim3 grid(8 * per_xcd), block(kBlock);
-    if (mode == MODE_FWD)
-        hipLaunchKernelGGL((stage_kernel_batched<R, MODE_FWD>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
-    else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel_batched<R, MODE_BWD>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
-    else
-        hipLaunchKernelGGL((stage_kernel_batched<R, MODE_HEUN2>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
-    return hipGetLastError();
-}
-
 }  // namespace
-
-hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s)
-{
-    return precision == PREC_FP64 ? launch_stage_r<double>(I, mode, s) : launch_stage_r<float>(I, mode, s);
-}
-
-hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
-                                int mode, int precision, hipStream_t s)
-{
-    return precision == PREC_FP64 ? launch_batched_r<double>(d_inst, d_tile_inst, total_tiles, mode, s)
-                                  : launch_batched_r<float>(d_inst, d_tile_inst, total_tiles, mode, s);
-}
 
 hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s)
 {
@@ -558,20 +172,30 @@ hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const float *a11, const float *a12, int64_t n, StatsPartial *d_partials,
+hipError_t launch_stats(const void *a11, const void *a12, int64_t n, int precision, StatsPartial *d_partials,
                         double *d_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(stats_partial_kernel, dim3(kStatsBlocks), dim3(256), 0, s, a11, a12, n, d_partials);
+    if (precision == PREC_FP64)
+        hipLaunchKernelGGL(stats_partial_kernel<double>, dim3(kStatsBlocks), dim3(256), 0, s,
+                           static_cast<const double *>(a11), static_cast<const double *>(a12), n, d_partials);
+    else
+        hipLaunchKernelGGL(stats_partial_kernel<float>, dim3(kStatsBlocks), dim3(256), 0, s,
+                           static_cast<const float *>(a11), static_cast<const float *>(a12), n, d_partials);
     hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kStatsBlocks), 0, s, d_partials, d_out);
     return hipGetLastError();
 }
 
-hipError_t launch_copy(float *dst, const float *src, int64_t n, hipStream_t s)
+hipError_t launch_copy(void *dst, const void *src, int64_t n, int precision, hipStream_t s)
 {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, n);
+    if (precision == PREC_FP64)
+        hipLaunchKernelGGL(copy_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<double *>(dst), static_cast<const double *>(src), n);
+    else
+        hipLaunchKernelGGL(copy_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<float *>(dst), static_cast<const float *>(src), n);
     return hipGetLastError();
 }
 

@@ -1,0 +1,18 @@
+// fdm_stage_f32.hip -- FP32-arithmetic instances of the stage kernels
+// (float32 state).  The compiler may fuse multiply-adds here.
+#include "fdm_stage.h"
+
+namespace fdm {
+
+hipError_t launch_stage_f32(const InstDev &I, int mode, hipStream_t s)
+{
+    return launch_stage_r<float, float>(I, mode, s);
+}
+
+hipError_t launch_stage_batched_f32(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
+                                    int mode, hipStream_t s)
+{
+    return launch_batched_r<float, float>(d_inst, d_tile_inst, total_tiles, mode, s);
+}
+
+}  // namespace fdm

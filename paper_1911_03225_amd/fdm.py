@@ -23,7 +23,7 @@ FDM_ERR_CFL, FDM_ERR_NONFINITE, FDM_ERR_UNSUPPORTED = 4, 5, 6
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2, "theta": 3, "superbee": 4}
 VELOCITIES = {"law": 0, "prescribed": 1}
 SCHEDULES = {"auto": 0, "batched": 1, "plain": 2}
-PRECISIONS = {"fp32": 0, "fp64": 1}
+PRECISIONS = {"fp32": 0, "fp64_arith": 1, "fp64": 2}
 
 
 class fdm_transport_desc(ctypes.Structure):
@@ -145,11 +145,11 @@ def desc(nx, ny, dx=1.0, dy=1.0, limiter="minmod", theta=1.0, time_order=2, cfl=
     return d
 
 
-def _ptr(t, shape, what):
+def _ptr(t, shape, what, dtype=torch.float32):
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch tensor" % what)
-    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
-        raise ValueError("%s must be a contiguous float32 CUDA tensor" % what)
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s CUDA tensor" % (what, str(dtype).replace("torch.", "")))
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s must have shape %s, got %s" % (what, tuple(shape), tuple(t.shape)))
     return t.data_ptr()
@@ -166,10 +166,12 @@ def _stream_handle(stream):
 class Context:
     """An fdm_ctx handle plus the Python objects it must keep alive."""
 
-    def __init__(self, handle, descs, keep):
+    def __init__(self, handle, descs, keep, precision=0):
         self.handle = handle
         self.descs = descs
         self._keep = keep
+        self.precision = precision
+        self.dtype = torch.float64 if precision == PRECISIONS["fp64"] else torch.float32
 
     @property
     def n(self):
@@ -204,7 +206,7 @@ def fdm_transport_init(descs, options=None, stream=None, keep=()):
     h = ctypes.c_void_p()
     st = lib.fdm_transport_init(arr, len(descs), opt, _stream_handle(stream), ctypes.byref(h))
     _check(st, "fdm_transport_init", None)
-    return Context(h, list(descs), keep)
+    return Context(h, list(descs), keep, options.precision if options is not None else 0)
 
 
 def _ptr_arrays(ctx, alpha11, alpha12):
@@ -215,8 +217,8 @@ def _ptr_arrays(ctx, alpha11, alpha12):
     p11 = (ctypes.c_void_p * ctx.n)()
     p12 = (ctypes.c_void_p * ctx.n)()
     for i, (a, b, d) in enumerate(zip(alpha11, alpha12, ctx.descs)):
-        p11[i] = _ptr(a, (d.ny, d.nx), "alpha11[%d]" % i)
-        p12[i] = _ptr(b, (d.ny, d.nx), "alpha12[%d]" % i)
+        p11[i] = _ptr(a, (d.ny, d.nx), "alpha11[%d]" % i, ctx.dtype)
+        p12[i] = _ptr(b, (d.ny, d.nx), "alpha12[%d]" % i, ctx.dtype)
     return p11, p12
 
 

@@ -5,9 +5,15 @@ from __future__ import annotations
 import numpy as np
 
 
-def to_dev(a):
+def to_dev(a, dtype=np.float32):
+    """Device copy; float64 copies hold the float32-rounded values exactly."""
     import torch
-    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32), dtype=dtype)
+    return torch.from_numpy(a).to("cuda:0")
+
+
+def state_dtype(options):
+    return np.float64 if (options or {}).get("precision") == "fp64" else np.float32
 
 
 def gpu_run(a11, a12, n_steps, snapshots=None, options=None, **desc_kw):
@@ -25,7 +31,7 @@ def gpu_run(a11, a12, n_steps, snapshots=None, options=None, **desc_kw):
     if v0f is not None:
         v0f = to_dev(v0f)
         keep.append(v0f)
-    t11, t12 = to_dev(a11), to_dev(a12)
+    t11, t12 = to_dev(a11, state_dtype(options)), to_dev(a12, state_dtype(options))
     ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, v0_field=v0f, **desc_kw), options=options, keep=keep)
     dt = fdm.fdm_transport_dt(ctx)
     out, done = [], 0

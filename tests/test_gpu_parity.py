@@ -9,7 +9,7 @@ shocks FP32 rounding moves a front sample by one ulp of the jump.
 import numpy as np
 import pytest
 
-from gpu_util import compare_run, gpu_run, oracle_problem, rel_l1, to_dev, tolerance
+from gpu_util import compare_run, gpu_run, oracle_problem, rel_l1, state_dtype, to_dev, tolerance
 from exact_solutions import densities, ring_phi_exact
 from paper_1911_03225_amd import workloads as W
 
@@ -77,6 +77,46 @@ def test_c2_full_size_short(fdm, oracle, limiter):
     a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
     dt, rep, g, o = compare_run(oracle, a11, a12, 12, every=6, limiter=limiter, cfl=0.4, v0=-1.0)
     _assert_report(rep, 12)
+
+
+def _both_precisions(oracle, a11, a12, snaps, **kw):
+    """GPU runs in float64-state and FP32 modes against one oracle run."""
+    runs = {}
+    for prec in ("fp64", "fp32"):
+        dt, out = gpu_run(a11, a12, snaps[-1], snapshots=snaps, options={"precision": prec}, **dict(kw))
+        runs[prec] = out
+    ny, nx = a11.shape
+    P = oracle_problem(oracle, nx, ny, dt, **kw)
+    o11, o12 = a11.astype(np.float64), a12.astype(np.float64)
+    done, rows = 0, []
+    for k, s in enumerate(snaps):
+        o11, o12 = oracle.run(P, o11, o12, s - done)
+        done = s
+        e = {p: rel_l1(runs[p][k][1], runs[p][k][2], o11, o12, a11, a12) for p in runs}
+        rows.append((s, e["fp64"], e["fp32"]))
+    return rows
+
+
+@pytest.mark.timeout(300)
+def test_c2_full_size_500_steps(fdm, oracle):
+    """C2 at full size for 500 steps: float64 state within 1e-5, FP32 within
+    its float32-state bound."""
+    a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
+    rows = _both_precisions(oracle, a11, a12, [100, 250, 500], limiter="superbee", cfl=0.4, v0=-1.0)
+    for s, e64, e32 in rows:
+        assert e64 <= tolerance(s), (s, e64, e32)
+        assert e32 <= fp32_loop_bound(s), (s, e64, e32)
+
+
+@pytest.mark.timeout(300)
+def test_c2_scaled_full_length(fdm, oracle):
+    """C2 scaled to 1024^2 (R = 150) for the full 2000 steps: the loop meets
+    its periodic images near step 905 and annihilates along the cell edges."""
+    a11, a12 = W.ring(1024, 1024, R=150.0, sigma=6.0)
+    rows = _both_precisions(oracle, a11, a12, [500, 1000, 1500, 2000], limiter="mc", cfl=0.4, v0=-1.0)
+    for s, e64, e32 in rows:
+        assert e64 <= tolerance(s), (s, e64, e32)
+        assert e32 <= fp32_loop_bound(s), (s, e64, e32)
 
 
 def _mean_radius(a11, a12, n):
@@ -261,8 +301,8 @@ def _run_many(F, cases, schedule, n_steps, use_run=False, precision="fp32"):
         if vf is not None:
             keep.append(vf)
         descs.append(F.desc(c["nx"], c["ny"], limiter=c["limiter"], cfl=0.4, v0=c["v0"], v0_field=vf))
-        t11.append(to_dev(c["a11"]))
-        t12.append(to_dev(c["a12"]))
+        t11.append(to_dev(c["a11"], state_dtype({"precision": precision})))
+        t12.append(to_dev(c["a12"], state_dtype({"precision": precision})))
     ctx = F.fdm_transport_init(descs, options={"schedule": schedule, "precision": precision}, keep=keep)
     if use_run:
         F.fdm_run(ctx, t11, t12, n_steps, 10)
@@ -274,7 +314,7 @@ def _run_many(F, cases, schedule, n_steps, use_run=False, precision="fp32"):
     return dts, [(x.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)) for x, y in zip(t11, t12)]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64_arith", "fp64"])
 def test_batched_equals_plain_bitwise_and_oracle(fdm, oracle, precision):
     from paper_1911_03225_amd import fdm as F
     cases = _mixed_instances()
@@ -282,7 +322,7 @@ def test_batched_equals_plain_bitwise_and_oracle(fdm, oracle, precision):
     dts2, batched = _run_many(F, cases, "batched", 40, precision=precision)
     assert dts == dts2
     # FP32 arithmetic on shock-dominated fronts: see test_shock_dominated_fp32
-    bound = tolerance(40) if precision == "fp64" else FP32_SHOCK_BOUND
+    bound = FP32_SHOCK_BOUND if precision == "fp32" else tolerance(40)
     for c, p, b, dt in zip(cases, plain, batched, dts):
         assert np.array_equal(p[0], b[0]) and np.array_equal(p[1], b[1])
         P = oracle_problem(oracle, c["nx"], c["ny"], dt, limiter=c["limiter"], v0=c["v0"], v0_field=c["v0_field"])
@@ -301,6 +341,20 @@ def test_batched_equals_plain_bitwise_and_oracle(fdm, oracle, precision):
 FP32_SHOCK_BOUND = 2e-3
 
 
+# Float32 *state*: rounding the densities to float32 after every stage is a
+# relative perturbation of 6e-8 that the scheme amplifies over hundreds of
+# steps (through the same discontinuity); the oracle itself, run with float32
+# storage between stages, drifts from its float64 run by 8e-5 (superbee),
+# 9e-6 (MC), 5e-5 (minmod) after 600 steps of a 512^2 loop.  The FP32 path is
+# held to 1e-6 per step (worst measured: 4.7e-4 after 1000 steps of the
+# 2048^2 loop); the float64-state mode to the 1e-5 per 1000 steps bar.
+def fp32_loop_bound(n_steps):
+    return max(tolerance(n_steps), 1e-6 * n_steps)
+
+
+FP32_LOOP_BOUND = fp32_loop_bound(100)
+
+
 def _shock_cases():
     cases = []
     for inst in W.c5_instances():
@@ -314,11 +368,12 @@ def _shock_cases():
     return cases
 
 
+@pytest.mark.parametrize("precision", ["fp64_arith", "fp64"])
 @pytest.mark.parametrize("case", range(5))
-def test_shock_dominated_fp64(fdm, oracle, case):
+def test_shock_dominated_fp64(fdm, oracle, case, precision):
     name, a11, a12, lim, v0, steps = _shock_cases()[case]
     dt, rep, g, o = compare_run(oracle, a11, a12, steps, every=max(1, steps // 5),
-                                options={"precision": "fp64"}, limiter=lim, cfl=0.4, v0=v0)
+                                options={"precision": precision}, limiter=lim, cfl=0.4, v0=v0)
     _assert_report(rep, steps)
 
 
@@ -380,3 +435,87 @@ def test_error_paths(fdm):
         F.fdm_transport_step(ctx, t11, t11, 1)
     assert e.value.status == F.FDM_ERR_INVALID_ARG
     F.fdm_destroy(ctx)
+
+
+# ----------------------------------------------- batched workload (C5)
+
+def _c5_subset():
+    """One instance per (size, velocity, limiter) of the batched recipe."""
+    seen, out = set(), []
+    for inst in W.c5_instances():
+        key = (inst.nx, inst.ny, inst.velocity, inst.limiter)
+        if key not in seen:
+            seen.add(key)
+            out.append(inst)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_subset_batched(fdm, oracle, precision):
+    """fp64: float64 state, 1e-5 for every instance.  fp32: the FP32 bar for
+    the instance kind (see FP32_LOOP_BOUND and FP32_SHOCK_BOUND)."""
+    import torch
+    from paper_1911_03225_amd import fdm as F
+    steps = 100
+    insts = _c5_subset()
+    arrays = [i.make() for i in insts]
+    keep, descs, t11, t12 = [], [], [], []
+    for i, (a11, a12, v) in zip(insts, arrays):
+        vf = to_dev(v) if v is not None else None
+        if vf is not None:
+            keep.append(vf)
+        descs.append(F.desc(i.nx, i.ny, limiter=i.limiter, cfl=0.4, v0=i.v0, v0_field=vf))
+        t11.append(to_dev(a11, state_dtype({"precision": precision})))
+        t12.append(to_dev(a12, state_dtype({"precision": precision})))
+    ctx = F.fdm_transport_init(descs, options={"schedule": "batched", "precision": precision}, keep=keep)
+    F.fdm_run(ctx, t11, t12, steps, 50, history=False)
+    torch.cuda.synchronize()
+    dts = [F.fdm_transport_dt(ctx, k) for k in range(len(insts))]
+    F.fdm_destroy(ctx)
+    failures = []
+    for i, (a11, a12, v), g11, g12, dt in zip(insts, arrays, t11, t12, dts):
+        P = oracle_problem(oracle, i.nx, i.ny, dt, limiter=i.limiter, v0=i.v0, v0_field=v)
+        o11, o12 = oracle.run(P, a11, a12, steps)
+        e = rel_l1(g11.cpu().numpy().astype(np.float64), g12.cpu().numpy().astype(np.float64), o11, o12, a11, a12)
+        smooth = i.init == "ring" and i.velocity == "uniform"
+        bound = tolerance(steps) if precision == "fp64" else (FP32_LOOP_BOUND if smooth else FP32_SHOCK_BOUND)
+        if not e <= bound:
+            failures.append((i.nx, i.ny, i.velocity, i.limiter, i.init, e))
+    assert not failures, failures
+
+
+# ------------------------------------------- FP64 mode: bit-for-bit oracle
+
+def _bitwise_cases():
+    cases = []
+    a11, a12 = W.c1_collision(64)
+    cases.append(("c1-collision", a11, a12, dict(limiter="minmod", cfl=0.5, v0=-1.0), 100))
+    a11, a12 = W.ring(130, 70, R=17.5, sigma=2.0)
+    cases.append(("ring-collision", a11, a12, dict(limiter="superbee", cfl=0.4, v0=-1.0), 60))
+    for inst in W.c5_instances():
+        if inst.nx == 128 and inst.init == "bands" and inst.velocity == "uniform" and inst.limiter == "mc":
+            a11, a12, _ = inst.make()
+            cases.append(("c5-bands-mc", a11, a12, dict(limiter="mc", cfl=0.4, v0=inst.v0), 100))
+            break
+    rng = np.random.default_rng(3)
+    a11, a12 = W.diagonal_bands(96, 80, rng, n_bands=6)
+    v0 = W.fourier_celerity(96, 80, rng, kmax=1)
+    cases.append(("bands-field", a11, a12, dict(limiter="theta", theta=1.5, cfl=0.45, v0_field=v0), 80))
+    a11, a12 = W.ring(61, 67, R=12.0, sigma=3.0)
+    cases.append(("euler-prescribed", a11, a12, dict(limiter="superbee", time_order=1, velocity="prescribed",
+                                                     V=(0.7, -0.4), cfl=0.5), 31))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_fp64_state_matches_oracle_bitwise(fdm, oracle, case):
+    """FDM_PRECISION_FP64 evaluates the oracle's operations in the oracle's
+    order with IEEE arithmetic: the results agree bit for bit."""
+    name, a11, a12, kw, steps = _bitwise_cases()[case]
+    dt, out = gpu_run(a11, a12, steps, options={"precision": "fp64"}, **dict(kw))
+    ny, nx = a11.shape
+    P = oracle_problem(oracle, nx, ny, dt, **kw)
+    o11, o12 = oracle.run(P, a11, a12, steps)
+    g11, g12 = out[-1][1], out[-1][2]
+    d = max(np.max(np.abs(g11 - o11)), np.max(np.abs(g12 - o12)))
+    assert d == 0.0, (name, d, rel_l1(g11, g12, o11, o12, a11, a12))
