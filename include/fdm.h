@@ -82,7 +82,7 @@ typedef enum fdm_velocity {
 
 /* One transport problem. */
 typedef struct fdm_transport_desc {
-    int32_t nx, ny;          /* pixel nodes, >= 1 each; nx*ny < 2^31             */
+    int32_t nx, ny;          /* pixel nodes, >= 1 each; nx*ny < 2^31, nx < 2^27  */
     double dx, dy;           /* grid spacings, > 0                              */
     int32_t limiter;         /* fdm_limiter                                     */
     double theta;            /* FDM_LIMITER_THETA only, in [1, 2]               */

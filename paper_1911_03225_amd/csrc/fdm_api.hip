@@ -83,6 +83,7 @@ std::string check_desc(const fdm_transport_desc &d)
 {
     if (d.nx < 1 || d.ny < 1) return "nx and ny must be >= 1";
     if ((int64_t)d.nx * d.ny >= (int64_t)1 << 31) return "nx*ny must be < 2^31";
+    if (d.nx >= 1 << 27) return "nx must be < 2^27 (a row of at most 1 GiB)";
     if (!finite_pos(d.dx) || !finite_pos(d.dy)) return "dx and dy must be finite and > 0";
     if (d.limiter < FDM_LIMITER_NONE || d.limiter > FDM_LIMITER_SUPERBEE) return "unknown limiter";
     if (d.limiter == FDM_LIMITER_THETA && !(d.theta >= 1.0 && d.theta <= 2.0))

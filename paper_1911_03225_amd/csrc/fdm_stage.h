@@ -36,16 +36,17 @@ namespace {
 
 // ---------------------------------------------------------------- lane moves
 
-// lane l receives lane l-1's value (lane 0 receives 0)
+// lane l receives lane l-1's value (lane 0 receives 0: bound_ctrl writes
+// zero where the source lane does not exist, so no old value is needed)
 __device__ __forceinline__ float from_left(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
 // lane l receives lane l+1's value (lane 63 receives 0)
 __device__ __forceinline__ float from_right(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 __device__ __forceinline__ double from_left(double v)
@@ -113,14 +114,31 @@ __host__ __device__ constexpr int limiter_kind(int lim)
 }
 
 // Limited slope at an edge from three consecutive values along its axis.
-// theta-minmod: minmod(theta*D+, (w+ - w-)/2, theta*D-), written as
-// max(min3, 0) + min(max3, 0): the minimum if all three are positive, the
-// maximum if all are negative, else zero.  Odd in w, exactly.
+// Every limiter here returns one of its candidate values (or zero), so the
+// result does not depend on how the selection is written.
+//
+// float: with med3(a, b, 0) = minmod(a, b) (the middle of a, b and 0 is the
+// smaller magnitude when the signs agree and 0 otherwise), theta-minmod is
+// med3(med3(theta*D+, theta*D-, 0), (w+ - w-)/2, 0), and superbee
+// picks the larger of minmod(2D-, D+) and minmod(D-, 2D+) -- both carry the
+// sign of D+ or are zero -- as med3(s1, s2, copysign(inf, D+)).
+//
+// double (no FP64 med3 on gfx950): theta-minmod as max(min3, 0) +
+// min(max3, 0), superbee as sign * max(min(2|D-|, |D+|), min(|D-|, 2|D+|))
+// when D- D+ > 0.
 template <int LK, typename R>
 __device__ __forceinline__ R limited_slope(R wm, R w0, R wp, R theta)
 {
     if constexpr (LK == LK_NONE) {
         return R(0);
+    } else if constexpr (sizeof(R) == 4 && LK == LK_SUPERBEE) {
+        const float dm = w0 - wm, dp = wp - w0;
+        const float s1 = __builtin_amdgcn_fmed3f(2.0f * dm, dp, 0.0f);
+        const float s2 = __builtin_amdgcn_fmed3f(dm, 2.0f * dp, 0.0f);
+        return __builtin_amdgcn_fmed3f(s1, s2, copysignf(__builtin_inff(), dp));
+    } else if constexpr (sizeof(R) == 4) {
+        const float a = theta * (wp - w0), b = 0.5f * (wp - wm), c = theta * (w0 - wm);
+        return __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, c, 0.0f), b, 0.0f);
     } else if constexpr (LK == LK_SUPERBEE) {
         const R dm = w0 - wm, dp = wp - w0;
         const R adm = vabs(dm), adp = vabs(dp);
@@ -161,10 +179,11 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         const R hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
         const R hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
         // Step 2: one-sided local speeds over the four combinations
-        const R ap = vmax(vmax(vmax(hx00, hx01), vmax(hx10, hx11)), R(0));
-        const R am = vmin(vmin(vmin(hx00, hx01), vmin(hx10, hx11)), R(0));
-        const R bp = vmax(vmax(vmax(hy00, hy01), vmax(hy10, hy11)), R(0));
-        const R bm = vmin(vmin(vmin(hy00, hy01), vmin(hy10, hy11)), R(0));
+        // (two three-operand max/min each)
+        const R ap = vmax(vmax(vmax(vmax(hx00, hx01), hx10), hx11), R(0));
+        const R am = vmin(vmin(vmin(vmin(hx00, hx01), hx10), hx11), R(0));
+        const R bp = vmax(vmax(vmax(vmax(hy00, hy01), hy10), hy11), R(0));
+        const R bm = vmin(vmin(vmin(vmin(hy00, hy01), hy10), hy11), R(0));
         // Steps 3-4 (dt -> 0): projection weights; 1/2 each and no viscosity
         // when nothing moves along that axis.  The sum keeps the order of
         // the definition (weighted corner values, then the two viscosity
@@ -260,30 +279,62 @@ __device__ __forceinline__ int next_row(int k, int ny)
     return k == ny ? 0 : k;
 }
 
-// Row `row` of a field, at this lane's byte offset: the row address is
-// wave-uniform (scalar registers), the offset a 32-bit lane value.
-template <typename T>
-__device__ __forceinline__ const T *row_ptr(const void *base, int row, int nx)
-{
-    return static_cast<const T *>(base) + (size_t)row * (size_t)nx;
-}
+// Rows are addressed through buffer resources: a wave-uniform row base
+// (scalar registers) plus this lane's 32-bit byte offset, so no access needs
+// 64-bit vector address arithmetic.  The hardware range check does the
+// masking: an offset at or beyond the row's byte size (kSkip for lanes that
+// must not write) loads 0 and drops stores, and a row built with `live`
+// false has size 0, which drops every lane.  Stores are therefore issued
+// unconditionally, with no branches around them, and the memory counter
+// waits stay exact.
+constexpr uint32_t kBufWord3 = 0x00020000u;   // gfx9: 32-bit data format, raw access
+constexpr uint32_t kSkip = 0x80000000u;       // > any row size (rows are < 2^31 bytes)
+
+template <typename T> struct RowRef {
+    __amdgpu_buffer_rsrc_t r;
+};
 
 template <typename T>
-__device__ __forceinline__ T at(const T *row, uint32_t off)
+__device__ __forceinline__ RowRef<T> row_ptr(const void *base, int row, int nx, bool live = true)
 {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(row) + off);
+    T *p = const_cast<T *>(static_cast<const T *>(base)) + (size_t)row * (size_t)nx;
+    const int bytes = live ? nx * (int)sizeof(T) : 0;
+    return RowRef<T>{__builtin_amdgcn_make_buffer_rsrc(p, 0, bytes, (int)kBufWord3)};
 }
 
-template <typename T>
-__device__ __forceinline__ void put(const T *row, uint32_t off, T v)
+__device__ __forceinline__ float at(RowRef<float> row, uint32_t off)
 {
-    *reinterpret_cast<T *>(const_cast<char *>(reinterpret_cast<const char *>(row)) + off) = v;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(row.r, (int)off, 0, 0));
 }
+
+__device__ __forceinline__ double at(RowRef<double> row, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(row.r, (int)off, 0, 0));
+}
+
+__device__ __forceinline__ void put(RowRef<float> row, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), row.r, (int)off, 0, 0);
+}
+
+__device__ __forceinline__ void put(RowRef<double> row, uint32_t off, double v)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), row.r, (int)off, 0, 0);
+}
+
+template <int P> struct Phase {
+    static constexpr int value = P;
+};
 
 // One wave: columns strip*60 .. strip*60+59 (lanes 2..61), rows
 // chunk*rows .. +rows-1, of one stage; arithmetic in R, state stored as S.
 // Loads run one row ahead of the arithmetic so their latency overlaps the
-// previous row.
+// previous row.  The row loop is unrolled four times by hand: every value
+// that moves along the sliding window (a loaded alpha_11 row is in flight,
+// then the row below, the current row and the row above; slopes, Hhat and
+// the other loads alternate between two registers) keeps one register for
+// its whole life, so no copies rotate the window.
 template <typename R, typename S, int LK, int VK, bool FIELD, int MODE>
 __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
 {
@@ -305,49 +356,62 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     const uint32_t off = (uint32_t)col * (uint32_t)sizeof(S);
     const uint32_t off_v = (uint32_t)col * 4u;
     const bool out_col = lane >= kHalo && lane < kHalo + kStrip && gcol < nx;
+    const uint32_t off_st = out_col ? off : kSkip;   // halo lanes do not write
     const int k0 = chunk * I.rows;
     const int nrows = min(I.rows, ny - k0);
 
-    // alpha_11 = -w_y on y-edges; the window holds rows k-2, k-1, k.
+    // alpha_11 = -w_y on y-edges.  Iteration i handles row k0+i; y[j % 4]
+    // holds alpha_11 of row k0+j (rows k0-1 .. k0+i+2 are live at most).
+    S y[4], wx_[2], b12_[2], b11_[2];
+    float v0_[2];
+    R sl[2], hh[2];
     int k = (k0 - 2) % ny;
     if (k < 0) k += ny;
     const R ym2 = R(at(row_ptr<S>(s11, k, nx), off));
     k = next_row(k, ny);
-    R ym1 = R(at(row_ptr<S>(s11, k, nx), off));
-    const int kprev0 = k;
+    y[3] = at(row_ptr<S>(s11, k, nx), off);
+    int kprev = k;
     k = next_row(k, ny);
-    R y0 = R(at(row_ptr<S>(s11, k, nx), off));
-    R sm1 = limited_slope<LK>(ym2, ym1, y0, theta);   // slope at edge k-1/2
-    R hprev = R(0);
-    int kprev = kprev0;
+    y[0] = at(row_ptr<S>(s11, k, nx), off);
+    sl[1] = limited_slope<LK>(ym2, R(y[3]), R(y[0]), theta);   // slope at edge k0-1/2
+    hh[1] = R(0);
 
     // first row's operands
     int kn = next_row(k, ny);
-    S f_wx = at(row_ptr<S>(s12, k, nx), off);
-    S f_yp1 = at(row_ptr<S>(s11, kn, nx), off);
-    float f_v0 = FIELD ? at(row_ptr<float>(I.v0f, k, nx), off_v) : 0.0f;
-    S f_b12 = kBase ? at(row_ptr<S>(d12, k, nx), off) : S(0);
-    S f_b11 = kBase ? at(row_ptr<S>(d11, kprev, nx), off) : S(0);
+    wx_[0] = at(row_ptr<S>(s12, k, nx), off);
+    y[1] = at(row_ptr<S>(s11, kn, nx), off);
+    v0_[0] = v0_[1] = 0.0f;
+    b12_[0] = b12_[1] = b11_[0] = b11_[1] = S(0);
+    if constexpr (FIELD) v0_[0] = at(row_ptr<float>(I.v0f, k, nx), off_v);
+    if constexpr (kBase) {
+        b12_[0] = at(row_ptr<S>(d12, k, nx), off);
+        b11_[0] = at(row_ptr<S>(d11, kprev, nx), off);
+    }
 
-    for (int it = 0; it <= nrows; ++it) {
-        const R wx = R(f_wx), yp1 = R(f_yp1);
-        const R v0 = FIELD ? R(f_v0) : R(I.v0);
-        const R b12 = R(f_b12), b11 = R(f_b11);
+    auto body = [&](int it, auto phase) {
+        constexpr int p = decltype(phase)::value;
+        constexpr int c = p & 1, n = c ^ 1;   // this row's and the next row's buffers
+        const R ym1 = R(y[(p + 3) & 3]), y0 = R(y[p]), yp1 = R(y[(p + 1) & 3]);
+        const R wx = R(wx_[c]);
+        const R v0 = FIELD ? R(v0_[c]) : R(I.v0);
+        const R b12 = R(b12_[c]), b11 = R(b11_[c]);
         const int knn = next_row(kn, ny);
-        if (it < nrows) {   // operands of the next row (wave-uniform branch)
-            f_wx = at(row_ptr<S>(s12, kn, nx), off);
-            f_yp1 = at(row_ptr<S>(s11, knn, nx), off);
-            if constexpr (FIELD) f_v0 = at(row_ptr<float>(I.v0f, kn, nx), off_v);
-            if constexpr (kBase) {
-                f_b12 = at(row_ptr<S>(d12, kn, nx), off);
-                f_b11 = at(row_ptr<S>(d11, k, nx), off);
-            }
+        // Operands of the next row.  Issued on every iteration (the last one
+        // reads a periodic row it does not use) so the wait for this row's
+        // operands never has to drain the loads just issued.
+        wx_[n] = at(row_ptr<S>(s12, kn, nx), off);
+        y[(p + 2) & 3] = at(row_ptr<S>(s11, knn, nx), off);
+        if constexpr (FIELD) v0_[n] = at(row_ptr<float>(I.v0f, kn, nx), off_v);
+        if constexpr (kBase) {
+            b12_[n] = at(row_ptr<S>(d12, kn, nx), off);
+            b11_[n] = at(row_ptr<S>(d11, k, nx), off);
         }
 
         // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
         const R s0 = limited_slope<LK>(ym1, y0, yp1, theta);
         const R pyp = -(y0 - R(0.5) * s0);
-        const R pym = -(ym1 + R(0.5) * sm1);
+        const R pym = -(ym1 + R(0.5) * sl[n]);
+        sl[c] = s0;
         // Steps 1-2 along x (alpha_12 = w_x), neighbours from adjacent lanes
         const R wl = from_left(wx), wr = from_right(wx);
         const R sx = limited_slope<LK>(wl, wx, wr, theta);
@@ -360,30 +424,38 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         else
             h = numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
         const R hr = from_right(h);
+        const R hprev = hh[n];
+        hh[c] = h;
 
-        if (out_col) {
-            if (it < nrows) {            // x-edge (j+1/2, k): d(alpha_12)/dt = -(Hhat_{j+1} - Hhat_j)/dx
-                R nv;
-                if constexpr (kF64) nv = wx + I.dtd * (-(hr - h) / I.dxd);
-                else nv = wx - cx * (hr - h);
-                if constexpr (kBase) nv = R(0.5) * b12 + R(0.5) * nv;
-                put(row_ptr<S>(d12, k, nx), off, S(nv));
-            }
-            if (it > 0) {                // y-edge (j, k-1/2): d(alpha_11)/dt = (Hhat_k - Hhat_{k-1})/dy
-                R nv;
-                if constexpr (kF64) nv = ym1 + I.dtd * ((h - hprev) / I.dyd);
-                else nv = ym1 + cy * (h - hprev);
-                if constexpr (kBase) nv = R(0.5) * b11 + R(0.5) * nv;
-                put(row_ptr<S>(d11, kprev, nx), off, S(nv));
-            }
+        {   // x-edge (j+1/2, k): d(alpha_12)/dt = -(Hhat_{j+1} - Hhat_j)/dx; not on the extra row
+            R nv;
+            if constexpr (kF64) nv = wx + I.dtd * (-(hr - h) / I.dxd);
+            else nv = wx - cx * (hr - h);
+            if constexpr (kBase) nv = R(0.5) * b12 + R(0.5) * nv;
+            put(row_ptr<S>(d12, k, nx, it < nrows), off_st, S(nv));
         }
-        hprev = h;
+        {   // y-edge (j, k-1/2): d(alpha_11)/dt = (Hhat_k - Hhat_{k-1})/dy; from the second row on
+            R nv;
+            if constexpr (kF64) nv = ym1 + I.dtd * ((h - hprev) / I.dyd);
+            else nv = ym1 + cy * (h - hprev);
+            if constexpr (kBase) nv = R(0.5) * b11 + R(0.5) * nv;
+            put(row_ptr<S>(d11, kprev, nx, it > 0), off_st, S(nv));
+        }
         kprev = k;
         k = kn;
         kn = knn;
-        ym1 = y0;
-        y0 = yp1;
-        sm1 = s0;
+    };
+
+    // it runs 0 .. nrows (one extra row: the Hhat row below the tile)
+    for (int it = 0;; it += 4) {
+        body(it, Phase<0>{});
+        if (it + 1 > nrows) break;
+        body(it + 1, Phase<1>{});
+        if (it + 2 > nrows) break;
+        body(it + 2, Phase<2>{});
+        if (it + 3 > nrows) break;
+        body(it + 3, Phase<3>{});
+        if (it + 4 > nrows) break;
     }
 }
 

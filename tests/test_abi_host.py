@@ -62,6 +62,7 @@ BAD = [
     (dict(nx=0), "nx and ny"),
     (dict(ny=-3), "nx and ny"),
     (dict(nx=65536, ny=65536), "2^31"),
+    (dict(nx=1 << 27, ny=1), "2^27"),
     (dict(dx=0.0), "dx and dy"),
     (dict(dy=float("nan")), "dx and dy"),
     (dict(limiter=7), "limiter"),
