@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64_arith", "fp64"])
     ap.add_argument("--no-c5", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--c5-steps", type=int, default=500)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one single-stage (Euler) step: its state copy-back is a plain copy kernel "
+                         "reading and writing 4*n*n bytes per array, the reference for HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -182,6 +185,14 @@ def main():
                 "hbm_achieved_gbs": round(BYTES_PER_CELL_STEP / 2 * cells / kernel_s / 1e9, 1)}
     final = hist[-1][0]
     fdm.fdm_destroy(ctx)
+
+    if args.copy_probe:
+        ctx1 = fdm.fdm_transport_init(fdm.desc(n, n, limiter=args.limiter, cfl=cfl, v0=-1.0, time_order=1),
+                                      options=options, stream=stream)
+        fdm.fdm_transport_step(ctx1, t11, t12, 1)
+        torch.cuda.synchronize()
+        fdm.fdm_destroy(ctx1)
+        log("bench: copy probe: one Euler step, copy kernel of %d bytes per array" % (cells * t11.element_size()))
 
     c5 = None
     if not args.no_c5:

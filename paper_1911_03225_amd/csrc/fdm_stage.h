@@ -178,25 +178,26 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         const R H00 = r00 * g00, H01 = r01 * g01, H10 = r10 * g10, H11 = r11 * g11;
         const R hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
         const R hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
-        // Step 2: one-sided local speeds over the four combinations
-        // (two three-operand max/min each)
-        const R ap = vmax(vmax(vmax(vmax(hx00, hx01), hx10), hx11), R(0));
-        const R am = vmin(vmin(vmin(vmin(hx00, hx01), hx10), hx11), R(0));
-        const R bp = vmax(vmax(vmax(vmax(hy00, hy01), hy10), hy11), R(0));
-        const R bm = vmin(vmin(vmin(vmin(hy00, hy01), hy10), hy11), R(0));
-        // Steps 3-4 (dt -> 0): projection weights; 1/2 each and no viscosity
-        // when nothing moves along that axis.  The sum keeps the order of
-        // the definition (weighted corner values, then the two viscosity
+        // Step 2: one-sided local speeds over the four combinations, bounded
+        // by +-FLT_MIN instead of 0 (two three-operand max/min each).  Then
+        // a+ - a- >= 2 FLT_MIN always: where nothing moves along an axis the
+        // weights come out as exactly 1/2 (2^-126 * rcp(2^-125)) and the
+        // viscosity as 0 (the product FLT_MIN^2 underflows), which is the
+        // scheme's degenerate case, with no compare or select; a one-sided
+        // speed of 0 becomes 1.2e-38, which moves nothing representable.
+        const R ap = vmax(vmax(vmax(vmax(hx00, hx01), hx10), hx11), kTiny);
+        const R am = vmin(vmin(vmin(vmin(hx00, hx01), hx10), hx11), -kTiny);
+        const R bp = vmax(vmax(vmax(vmax(hy00, hy01), hy10), hy11), kTiny);
+        const R bm = vmin(vmin(vmin(vmin(hy00, hy01), hy10), hy11), -kTiny);
+        // Steps 3-4 (dt -> 0): projection weights.  The sum keeps the order
+        // of the definition (weighted corner values, then the two viscosity
         // terms): rewriting it, e.g. with w_+ = 1 - w_-, lets FMA
         // contraction turn exact cancellations between equal corner values
         // into product rounding errors, which the kink of |p| at p = 0
         // then amplifies.
-        const R da = ap - am, db = bp - bm;
-        const bool mx = da >= kTiny, my = db >= kTiny;
-        const R ia = mx ? Arith<R>::rcp(da) : R(0);
-        const R ib = my ? Arith<R>::rcp(db) : R(0);
-        const R wxm = mx ? ap * ia : R(0.5), wxp = mx ? -am * ia : R(0.5);
-        const R wym = my ? bp * ib : R(0.5), wyp = my ? -bm * ib : R(0.5);
+        const R ia = Arith<R>::rcp(ap - am), ib = Arith<R>::rcp(bp - bm);
+        const R wxm = ap * ia, wxp = -am * ia;
+        const R wym = bp * ib, wyp = -bm * ib;
         const R visc_x = ap * am * ia, visc_y = bp * bm * ib;
         return wxm * (wym * H00 + wyp * H01) + wxp * (wym * H10 + wyp * H11)
              + visc_x * (pxp - pxm) + visc_y * (pyp - pym);
@@ -396,15 +397,16 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         const R v0 = FIELD ? R(v0_[c]) : R(I.v0);
         const R b12 = R(b12_[c]), b11 = R(b11_[c]);
         const int knn = next_row(kn, ny);
-        // Operands of the next row.  Issued on every iteration (the last one
-        // reads a periodic row it does not use) so the wait for this row's
-        // operands never has to drain the loads just issued.
-        wx_[n] = at(row_ptr<S>(s12, kn, nx), off);
-        y[(p + 2) & 3] = at(row_ptr<S>(s11, knn, nx), off);
-        if constexpr (FIELD) v0_[n] = at(row_ptr<float>(I.v0f, kn, nx), off_v);
+        // Operands of the next row.  Issued on every iteration, so the wait
+        // for this row's operands never has to drain the loads just issued;
+        // on the last one the rows are empty (no memory is read).
+        const bool more = it < nrows;
+        wx_[n] = at(row_ptr<S>(s12, kn, nx, more), off);
+        y[(p + 2) & 3] = at(row_ptr<S>(s11, knn, nx, more), off);
+        if constexpr (FIELD) v0_[n] = at(row_ptr<float>(I.v0f, kn, nx, more), off_v);
         if constexpr (kBase) {
-            b12_[n] = at(row_ptr<S>(d12, kn, nx), off);
-            b11_[n] = at(row_ptr<S>(d11, k, nx), off);
+            b12_[n] = at(row_ptr<S>(d12, kn, nx, more), off);
+            b11_[n] = at(row_ptr<S>(d11, k, nx, more), off);
         }
 
         // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
