@@ -461,9 +461,12 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     }
 }
 
-// Hardware places block b on XCD b % 8.  Give each XCD a contiguous run of
-// tiles (vertically adjacent chunks of the same strips) so halo rows are
-// re-read from that XCD's L2.
+// Tiles are numbered row band first (tile = chunk * strips + strip), so
+// consecutive waves -- the four of a block, and neighbouring blocks -- are
+// side-by-side strips walking the same rows at the same time: the 128-byte
+// lines shared at strip edges are fetched once and hit in cache for the
+// neighbour.  Hardware places block b on XCD b % 8; each XCD gets a
+// contiguous run of tiles, i.e. a band of rows across the grid.
 __device__ __forceinline__ int64_t xcd_tile(int blocks_per_xcd)
 {
     const int b = blockIdx.x;
@@ -478,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
     const int t = (int)tile;
-    run_tile<R, S, LK, VK, FIELD, MODE>(I, t / I.chunks, t % I.chunks, threadIdx.x & 63);
+    run_tile<R, S, LK, VK, FIELD, MODE>(I, t % I.strips, t / I.strips, threadIdx.x & 63);
 }
 
 // Batched: one launch for every tile of every instance; tile_inst maps a
@@ -493,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__
     if (tile >= total_tiles) return;
     const InstDev I = insts[tile_inst[tile]];
     const int local = (int)(tile - I.tile_begin);
-    const int strip = local / I.chunks, chunk = local % I.chunks;
+    const int strip = local % I.strips, chunk = local / I.strips;
     const int lane = threadIdx.x & 63;
     const int lk = limiter_kind(I.limiter);
     if (I.vkind == VK_PRESCRIBED) {
