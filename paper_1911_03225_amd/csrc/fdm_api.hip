@@ -109,24 +109,27 @@ float round_down_float(double x)
 }
 
 // Rows per wave tile.  Each tile recomputes one extra row of Hhat and
-// reloads four rows of alpha_11, so long tiles are cheaper per row; but the
-// grid should still offer at least one wave per wave slot of the chip
-// (256 CUs x 4 SIMDs x 8 waves) so every SIMD has latency to hide.  Take the
-// longest tile in {8, 16, 32} meeting that, else 8 (measured on MI355X:
-// 2048^2 runs fastest with 8, 4 and 16 are 9% and 2% slower).
-int pick_rows(const fdm_transport_desc &d, int requested)
+// re-reads a few boundary rows, so long tiles are cheaper per row; but the
+// launch should give every SIMD about six waves (6144 on 256 CUs x 4 SIMDs)
+// to hide memory latency.  `strip_rows` is the number of (strip, row) pairs
+// the launch covers (over all instances of a batched launch).  The result
+// is that count / 6144 rounded up to a multiple of 4 and kept in [4, 32].
+// Measured on MI355X (superbee, Heun): 1024^2 is fastest with 4 rows,
+// 2048^2 with 12 (16 is 6% slower), 4096^2 and 8192^2 with 32 (64 is 6-9%
+// slower).
+int pick_rows(int64_t strip_rows, int ny, int requested)
 {
-    if (requested > 0) return std::min(requested, d.ny);
-    const int64_t strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
-    const int64_t slots = 256 * 4 * 8;
-    int rows = 8;
-    for (int r : {32, 16}) {
-        if (strips * ((d.ny + r - 1) / r) >= slots) {
-            rows = r;
-            break;
-        }
-    }
-    return std::min(rows, d.ny);
+    if (requested > 0) return std::min(requested, ny);
+    const int64_t target_waves = 256 * 4 * 6;
+    int64_t rows = (strip_rows + target_waves - 1) / target_waves;
+    rows = (rows + 3) / 4 * 4;
+    rows = std::max<int64_t>(4, std::min<int64_t>(32, rows));
+    return (int)std::min<int64_t>(rows, ny);
+}
+
+int64_t strip_rows_of(const fdm_transport_desc &d)
+{
+    return (int64_t)((d.nx + fdm::kStrip - 1) / fdm::kStrip) * d.ny;
 }
 
 void release(fdm_ctx *c)
@@ -286,6 +289,8 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     c->schedule = opt.schedule;
     c->precision = opt.precision;
     c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN;
+    int64_t batch_strip_rows = 0;
+    for (int i = 0; i < n_instances; ++i) batch_strip_rows += strip_rows_of(descs[i]);
     c->desc.assign(descs, descs + n_instances);
     c->inst.resize(n_instances);
     c->dt.resize(n_instances);
@@ -375,7 +380,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         I.theta = (float)I.thetad;
         I.limiter = d.limiter;
         I.vkind = d.velocity;
-        I.rows = pick_rows(d, opt.tile_rows);
+        I.rows = pick_rows(c->batched ? batch_strip_rows : strip_rows_of(d), d.ny, opt.tile_rows);
         I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
         I.chunks = (d.ny + I.rows - 1) / I.rows;
         I.tile_begin = tile;

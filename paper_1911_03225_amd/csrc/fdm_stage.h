@@ -330,12 +330,13 @@ template <int P> struct Phase {
 
 // One wave: columns strip*60 .. strip*60+59 (lanes 2..61), rows
 // chunk*rows .. +rows-1, of one stage; arithmetic in R, state stored as S.
-// Loads run one row ahead of the arithmetic so their latency overlaps the
-// previous row.  The row loop is unrolled four times by hand: every value
-// that moves along the sliding window (a loaded alpha_11 row is in flight,
-// then the row below, the current row and the row above; slopes, Hhat and
-// the other loads alternate between two registers) keeps one register for
-// its whole life, so no copies rotate the window.
+// Loads run kAhead rows ahead of the arithmetic, so each load has the
+// arithmetic of kAhead rows to arrive.  The row loop is unrolled eight times
+// by hand: every value on the sliding window (alpha_11 rows from in flight
+// down to the row below the current one; the other loads; slopes and Hhat)
+// sits in a ring slot fixed by the row number, so no copies rotate it.
+constexpr int kAhead = 2;
+
 template <typename R, typename S, int LK, int VK, bool FIELD, int MODE>
 __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
 {
@@ -357,99 +358,116 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     const uint32_t off = (uint32_t)col * (uint32_t)sizeof(S);
     const uint32_t off_v = (uint32_t)col * 4u;
     const bool out_col = lane >= kHalo && lane < kHalo + kStrip && gcol < nx;
-    const uint32_t off_st = out_col ? off : kSkip;   // halo lanes do not write
     const int k0 = chunk * I.rows;
     const int nrows = min(I.rows, ny - k0);
+    const uint32_t off_st = out_col ? off : kSkip;   // halo lanes do not write
 
-    // alpha_11 = -w_y on y-edges.  Iteration i handles row k0+i; y[j % 4]
-    // holds alpha_11 of row k0+j (rows k0-1 .. k0+i+2 are live at most).
-    S y[4], wx_[2], b12_[2], b11_[2];
-    float v0_[2];
+    // Iteration i (0 .. nrows; the last one only completes the y-edges)
+    // handles row k0+i.  Ring slots: alpha_11 of row k0+j in y[j & 7] (rows
+    // k0+i-1 .. k0+i+kAhead+1 are live), the other loads of row k0+j in
+    // slot j & 3, slope and Hhat of row k0+j in slot j & 1.
+    S y[8], wx_[4], b12_[4], b11_[4];
+    float v0_[4];
     R sl[2], hh[2];
+    for (int j = 0; j < 4; ++j) {
+        v0_[j] = 0.0f;
+        b12_[j] = b11_[j] = S(0);
+    }
     int k = (k0 - 2) % ny;
     if (k < 0) k += ny;
     const R ym2 = R(at(row_ptr<S>(s11, k, nx), off));
     k = next_row(k, ny);
-    y[3] = at(row_ptr<S>(s11, k, nx), off);
+    y[7] = at(row_ptr<S>(s11, k, nx), off);
     int kprev = k;
     k = next_row(k, ny);
     y[0] = at(row_ptr<S>(s11, k, nx), off);
-    sl[1] = limited_slope<LK>(ym2, R(y[3]), R(y[0]), theta);   // slope at edge k0-1/2
+    sl[1] = limited_slope<LK>(ym2, R(y[7]), R(y[0]), theta);   // slope at edge k0-1/2
     hh[1] = R(0);
 
-    // first row's operands
-    int kn = next_row(k, ny);
-    wx_[0] = at(row_ptr<S>(s12, k, nx), off);
-    y[1] = at(row_ptr<S>(s11, kn, nx), off);
-    v0_[0] = v0_[1] = 0.0f;
-    b12_[0] = b12_[1] = b11_[0] = b11_[1] = S(0);
-    if constexpr (FIELD) v0_[0] = at(row_ptr<float>(I.v0f, k, nx), off_v);
-    if constexpr (kBase) {
-        b12_[0] = at(row_ptr<S>(d12, k, nx), off);
-        b11_[0] = at(row_ptr<S>(d11, kprev, nx), off);
+    // Loads of the first kAhead rows.  kf: row of the next fetch (k0+i+kAhead
+    // at iteration i), kf1 the row after it, kfm the row before it.
+    int kfm = kprev, kf = k;
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+        const int kf1 = next_row(kf, ny);
+        const bool live = j <= nrows;
+        wx_[j] = at(row_ptr<S>(s12, kf, nx, live), off);
+        y[j + 1] = at(row_ptr<S>(s11, kf1, nx, live), off);
+        if constexpr (FIELD) v0_[j] = at(row_ptr<float>(I.v0f, kf, nx, live), off_v);
+        if constexpr (kBase) {
+            b12_[j] = at(row_ptr<S>(d12, kf, nx, live), off);
+            b11_[j] = at(row_ptr<S>(d11, kfm, nx, live), off);
+        }
+        kfm = kf;
+        kf = kf1;
     }
+    int kf1 = next_row(kf, ny);
 
     auto body = [&](int it, auto phase) {
         constexpr int p = decltype(phase)::value;
-        constexpr int c = p & 1, n = c ^ 1;   // this row's and the next row's buffers
-        const R ym1 = R(y[(p + 3) & 3]), y0 = R(y[p]), yp1 = R(y[(p + 1) & 3]);
+        constexpr int c = p & 3, f = (p + kAhead) & 3;   // this row's and the fetched row's slots
+        constexpr int h = p & 1, hp = h ^ 1;              // this row's and the previous row's slope / Hhat
+        const R ym1 = R(y[(p + 7) & 7]), y0 = R(y[p]), yp1 = R(y[(p + 1) & 7]);
         const R wx = R(wx_[c]);
         const R v0 = FIELD ? R(v0_[c]) : R(I.v0);
         const R b12 = R(b12_[c]), b11 = R(b11_[c]);
-        const int knn = next_row(kn, ny);
-        // Operands of the next row.  Issued on every iteration, so the wait
-        // for this row's operands never has to drain the loads just issued;
-        // on the last one the rows are empty (no memory is read).
-        const bool more = it < nrows;
-        wx_[n] = at(row_ptr<S>(s12, kn, nx, more), off);
-        y[(p + 2) & 3] = at(row_ptr<S>(s11, knn, nx, more), off);
-        if constexpr (FIELD) v0_[n] = at(row_ptr<float>(I.v0f, kn, nx, more), off_v);
-        if constexpr (kBase) {
-            b12_[n] = at(row_ptr<S>(d12, kn, nx, more), off);
-            b11_[n] = at(row_ptr<S>(d11, k, nx, more), off);
+        // Operands of row k0+it+kAhead.  Issued on every iteration, so the
+        // wait for this row's operands never has to drain loads just issued;
+        // past the tile the rows are empty (no memory is read).
+        {
+            const bool live = it + kAhead <= nrows;
+            wx_[f] = at(row_ptr<S>(s12, kf, nx, live), off);
+            y[(p + kAhead + 1) & 7] = at(row_ptr<S>(s11, kf1, nx, live), off);
+            if constexpr (FIELD) v0_[f] = at(row_ptr<float>(I.v0f, kf, nx, live), off_v);
+            if constexpr (kBase) {
+                b12_[f] = at(row_ptr<S>(d12, kf, nx, live), off);
+                b11_[f] = at(row_ptr<S>(d11, kfm, nx, live), off);
+            }
+            kfm = kf;
+            kf = kf1;
+            kf1 = next_row(kf1, ny);
         }
 
         // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
         const R s0 = limited_slope<LK>(ym1, y0, yp1, theta);
         const R pyp = -(y0 - R(0.5) * s0);
-        const R pym = -(ym1 + R(0.5) * sl[n]);
-        sl[c] = s0;
+        const R pym = -(ym1 + R(0.5) * sl[hp]);
+        sl[h] = s0;
         // Steps 1-2 along x (alpha_12 = w_x), neighbours from adjacent lanes
         const R wl = from_left(wx), wr = from_right(wx);
         const R sx = limited_slope<LK>(wl, wx, wr, theta);
         const R pxp = wx - R(0.5) * sx;
         const R pxm = from_left(wx + R(0.5) * sx);
         // Steps 2-4
-        R h;
+        R hv;
         if constexpr (kF64)
-            h = numerical_hamiltonian_ieee<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
+            hv = numerical_hamiltonian_ieee<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
         else
-            h = numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
-        const R hr = from_right(h);
-        const R hprev = hh[n];
-        hh[c] = h;
+            hv = numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
+        const R hr = from_right(hv);
+        const R hprev = hh[hp];
+        hh[h] = hv;
 
         {   // x-edge (j+1/2, k): d(alpha_12)/dt = -(Hhat_{j+1} - Hhat_j)/dx; not on the extra row
             R nv;
-            if constexpr (kF64) nv = wx + I.dtd * (-(hr - h) / I.dxd);
-            else nv = wx - cx * (hr - h);
+            if constexpr (kF64) nv = wx + I.dtd * (-(hr - hv) / I.dxd);
+            else nv = wx - cx * (hr - hv);
             if constexpr (kBase) nv = R(0.5) * b12 + R(0.5) * nv;
             put(row_ptr<S>(d12, k, nx, it < nrows), off_st, S(nv));
         }
         {   // y-edge (j, k-1/2): d(alpha_11)/dt = (Hhat_k - Hhat_{k-1})/dy; from the second row on
             R nv;
-            if constexpr (kF64) nv = ym1 + I.dtd * ((h - hprev) / I.dyd);
-            else nv = ym1 + cy * (h - hprev);
+            if constexpr (kF64) nv = ym1 + I.dtd * ((hv - hprev) / I.dyd);
+            else nv = ym1 + cy * (hv - hprev);
             if constexpr (kBase) nv = R(0.5) * b11 + R(0.5) * nv;
             put(row_ptr<S>(d11, kprev, nx, it > 0), off_st, S(nv));
         }
         kprev = k;
-        k = kn;
-        kn = knn;
+        k = next_row(k, ny);
     };
 
     // it runs 0 .. nrows (one extra row: the Hhat row below the tile)
-    for (int it = 0;; it += 4) {
+    for (int it = 0;; it += 8) {
         body(it, Phase<0>{});
         if (it + 1 > nrows) break;
         body(it + 1, Phase<1>{});
@@ -458,6 +476,14 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         if (it + 3 > nrows) break;
         body(it + 3, Phase<3>{});
         if (it + 4 > nrows) break;
+        body(it + 4, Phase<4>{});
+        if (it + 5 > nrows) break;
+        body(it + 5, Phase<5>{});
+        if (it + 6 > nrows) break;
+        body(it + 6, Phase<6>{});
+        if (it + 7 > nrows) break;
+        body(it + 7, Phase<7>{});
+        if (it + 8 > nrows) break;
     }
 }
 
