@@ -39,7 +39,7 @@ OPS_PER_NODE_STAGE = 120
 # counters (FETCH_SIZE and WRITE_SIZE passes, each calibrated by a plain copy
 # kernel of known size) and tied to the kernel sources it was measured on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_c2_2048_fp32_traffic.json")
-KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_api.hip"]
+KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_kernels.hip"]
 STAGE_NAMES = {"fwd": "stage_kernel<float, float, 2, 0, false, 0>",
                "heun2": "stage_kernel<float, float, 2, 0, false, 2>"}
 COPY_NAME = "copy_kernel<float>"
@@ -70,6 +70,7 @@ def _counter_means(directory, counter):
     # same kernel name on a larger grid, so each family keeps its most
     # frequent grid size (the bench launches)
     vals = collections.defaultdict(list)
+    grids = collections.defaultdict(list)
     for f in files:
         for r in csv.DictReader(open(f)):
             if r["Counter_Name"] != counter:
@@ -80,27 +81,42 @@ def _counter_means(directory, counter):
                 fam = ["copy"]
             if fam:
                 vals[(fam[0], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
-    out = {}
+    out, grid = {}, {}
     for k in list(STAGE_NAMES) + ["copy"]:
         groups = [(len(v), g, v) for (fam, g), v in vals.items() if fam == k]
         if not groups:
             raise SystemExit("no %s samples for %s in %s" % (counter, k, directory))
-        v = max(groups)[2]
+        _, grid[k], v = max(groups)
         out[k] = sum(v) / len(v)
-    return out, len(vals)
+    return out, grid
+
+
+def rows_from_grid(grid_threads, n):
+    """Tile height of a stage launch on an n x n grid from its thread count:
+    blocks of 4 waves, rounded up to a multiple of 8 blocks (one per XCD)."""
+    strips = -(-n // 60)
+    for r in range(1, n + 1):
+        tiles = strips * -(-n // r)
+        blocks = -(-tiles // 4)
+        blocks = -(-blocks // 8) * 8
+        if blocks * 256 == grid_threads:
+            return r
+    return None
 
 
 def write_traffic_summary(fetch_dir, write_dir, out, copy_n, grid_n):
     """Per-launch traffic of the two stage kernels from counter passes.  The
     copy kernel reads and writes 4*copy_n^2 bytes: the ratio to what each
     counter reports for it is that counter's calibration factor."""
-    fetch, _ = _counter_means(fetch_dir, "FETCH_SIZE")
+    fetch, grid = _counter_means(fetch_dir, "FETCH_SIZE")
     write, _ = _counter_means(write_dir, "WRITE_SIZE")
+    rows = rows_from_grid(grid["fwd"], grid_n)
     copy_kib = 4.0 * copy_n * copy_n / 1024.0
     ff, wf = copy_kib / fetch["copy"], copy_kib / write["copy"]
     per = {k: {"fetch_kib": round(fetch[k], 1), "write_kib": round(write[k], 1),
                "bytes": round((fetch[k] * ff + write[k] * wf) * 1024.0)} for k in STAGE_NAMES}
-    summary = {"kernel_source_sha256": kernel_source_hash(), "grid": grid_n, "copy_probe_n": copy_n,
+    summary = {"kernel_source_sha256": kernel_source_hash(), "grid": grid_n, "tile_rows": rows,
+               "copy_probe_n": copy_n,
                "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
                "copy_fetch_kib": round(fetch["copy"], 1), "copy_write_kib": round(write["copy"], 1),
                "stage": per,
@@ -112,15 +128,17 @@ def write_traffic_summary(fetch_dir, write_dir, out, copy_n, grid_n):
 
 def load_traffic(grid_n, precision, limiter, tile_rows):
     """Bytes per stage launch for this workload, or None when no summary was
-    measured on the current kernel sources and configuration."""
-    if precision != "fp32" or limiter != "superbee" or tile_rows != 0 or not os.path.exists(TRAFFIC_FILE):
+    measured on the current kernel sources and configuration (tile_rows: the
+    height the timed launches used)."""
+    if precision != "fp32" or limiter != "superbee" or not os.path.exists(TRAFFIC_FILE):
         return None
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("grid") != grid_n:
+    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("grid") != grid_n \
+            or t.get("tile_rows") != tile_rows:
         return None
     return t
 
@@ -130,7 +148,7 @@ def _make_instance(inst):
     return a11, a12, v0
 
 
-def batched_vs_plain(fdm, workloads, K, log):
+def batched_vs_plain(fdm, workloads, K, log, autotune=True):
     """The batched workload (384 instances, ~90M nodes): one K-step chunk as
     one graph of batched launches against one launch per instance per stage."""
     import concurrent.futures as cf
@@ -154,10 +172,16 @@ def batched_vs_plain(fdm, workloads, K, log):
     stream = torch.cuda.current_stream()
     out = {}
     finals = {}
+    rows = {}
     for sched in ("batched", "plain"):
         s11 = [b.clone() for b in base11]
         s12 = [b.clone() for b in base12]
         ctx = fdm.fdm_transport_init(descs, options={"schedule": sched}, stream=stream, keep=fields)
+        if autotune:
+            trials = fdm.fdm_autotune(ctx, s11, s12, trial_steps=2)
+            log("bench[c5]: %s autotune: %s" % (sched, ", ".join("%d rows %.3f ms" % (
+                t["tile_rows"], 1e3 * t["seconds_per_step"]) for t in trials)))
+        rows[sched] = fdm.fdm_tile_rows(ctx, 0)
         if sched == "batched":
             fdm.fdm_run(ctx, s11, s12, K, K, history=False)      # capture + warm
         else:
@@ -182,6 +206,7 @@ def batched_vs_plain(fdm, workloads, K, log):
         stats = fdm.fdm_transport_stats(ctx, s11, s12, allow_nonfinite=True)
         fdm.fdm_destroy(ctx)
         out[sched] = {"seconds": round(dt_s, 4), "cell_updates_per_s": round(nodes * K / dt_s, 1),
+                      "tile_rows": rows[sched],
                       "nonfinite_instances": sum(1 for st in stats if st["nonfinite"])}
         finals[sched] = (s11, s12)
         log("bench[c5]: %s %d steps in %.3f s (%.3e cell-updates/s)" % (sched, K, dt_s, nodes * K / dt_s))
@@ -203,7 +228,9 @@ def main():
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--tile-rows", type=int, default=0, help="0: the library's default rule")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep --tile-rows instead of timing the candidate tilings first (fdm_autotune)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64_arith", "fp64"])
     ap.add_argument("--no-c5", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--c5-steps", type=int, default=500)
@@ -245,8 +272,14 @@ def main():
     ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter=args.limiter, cfl=cfl, v0=-1.0), options=options,
                                  stream=stream)
     dt = fdm.fdm_transport_dt(ctx)
+    tuning = None
+    if not args.no_autotune:
+        tuning = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=10)
+        log("bench: autotune: %s" % ", ".join("%d rows %.2f us" % (t["tile_rows"], 1e6 * t["seconds_per_step"])
+                                               for t in tuning))
+    rows_used = fdm.fdm_tile_rows(ctx, 0)
 
-    log("bench: warmup %d steps + one captured chunk of %d" % (W, K))
+    log("bench: warmup %d steps + one captured chunk of %d (%d-row tiles)" % (W, K, rows_used))
     fdm.fdm_transport_step(ctx, t11, t12, W)
     fdm.fdm_run(ctx, t11, t12, K, K)          # captures the chunk graph
     torch.cuda.synchronize()
@@ -273,7 +306,7 @@ def main():
     kernel_s = t_med / launches
     ops_per_launch = OPS_PER_NODE_STAGE * cells
     achieved = ops_per_launch / kernel_s / 1e12
-    tr = load_traffic(n, args.precision, args.limiter, args.tile_rows)
+    tr = load_traffic(n, args.precision, args.limiter, rows_used)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
                 "traffic": tr["bytes_per_launch"] if tr else None,
@@ -301,7 +334,7 @@ def main():
 
     c5 = None
     if not args.no_c5:
-        c5 = batched_vs_plain(fdm, workloads, args.c5_steps, log)
+        c5 = batched_vs_plain(fdm, workloads, args.c5_steps, log, autotune=not args.no_autotune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -330,7 +363,9 @@ def main():
         "config": {"workload": "single loop %dx%d (ring R=%g sigma=%g), LAW v0=-1, %s, Heun, CFL %g"
                                % (n, n, R, sigma, args.limiter, cfl),
                    "grid": [n, n], "limiter": args.limiter, "cfl": cfl, "dt": dt, "time_order": 2,
-                   "chunk_steps": K, "tile_rows": args.tile_rows, "precision": args.precision},
+                   "chunk_steps": K, "tile_rows": rows_used,
+                   "tiling": "autotuned" if tuning else ("fixed" if args.tile_rows else "default rule"),
+                   "precision": args.precision},
         "hbm_frac_algorithmic": round(value * BYTES_PER_CELL_STEP / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,

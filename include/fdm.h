@@ -213,6 +213,33 @@ fdm_status fdm_run(fdm_ctx *ctx, const fdm_loading *loading, void *const *alpha1
 /* The float32 time step of instance i (after init), or -1 on a bad argument. */
 double fdm_transport_dt(const fdm_ctx *ctx, int32_t instance);
 
+/* Rows per wave tile that instance i uses (the option, the default rule or
+ * the autotuner's choice), or -1 on a bad argument. */
+int32_t fdm_tile_rows(const fdm_ctx *ctx, int32_t instance);
+
+/* One timed candidate of fdm_autotune. */
+typedef struct fdm_tune_trial {
+    int32_t tile_rows;       /* rows per wave tile tried (all instances)        */
+    int32_t schedule;        /* FDM_SCHEDULE_BATCHED or FDM_SCHEDULE_PLAIN      */
+    double seconds_per_step; /* median of two timed runs of trial_steps steps   */
+} fdm_tune_trial;
+
+/* Autotuner for the launch shape (not a step of the paper's method: tiling
+ * changes no result bit, only speed).  Copies the given state into scratch
+ * memory, and on that copy times trial_steps (>= 1) steps for each candidate
+ * tile height in {4, 8, 12, 16, 24, 32, 48, 64} (heights above the tallest
+ * instance are skipped) and, for a context of several instances created with
+ * FDM_SCHEDULE_AUTO, for both the batched and the plain schedule.  The
+ * context then keeps the fastest candidate.  alpha11/alpha12 are read, never
+ * written; the step count and diagnostics baseline are unchanged.  Up to
+ * max_trials measured candidates are written to trials (may be NULL when
+ * max_trials is 0) and their number to *n_trials (may be NULL).  Synchronous:
+ * returns after the last trial.  Allocates the scratch copy (state size) for
+ * the duration of the call.  Errors: FDM_ERR_INVALID_ARG for bad arguments,
+ * FDM_ERR_OUT_OF_MEMORY, FDM_ERR_DEVICE. */
+fdm_status fdm_autotune(fdm_ctx *ctx, void *const *alpha11, void *const *alpha12, int32_t trial_steps,
+                        fdm_tune_trial *trials, int32_t max_trials, int32_t *n_trials);
+
 /* Release the context and its workspace (waits for its pending work).
  * NULL is a no-op. */
 void fdm_destroy(fdm_ctx *ctx);

@@ -48,6 +48,9 @@ struct fdm_ctx {
     hipGraphExec_t graph = nullptr;
     int32_t graph_steps = 0;
     std::vector<void *> graph_a11, graph_a12;
+    size_t elem = sizeof(float);            // bytes per state value
+    int64_t tile_capacity = 0;              // entries of d_tile_inst
+    int32_t requested_rows = 0;             // tile rows asked for (0: default rule)
     bool sticky = false;
     std::string err;
 };
@@ -214,6 +217,52 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
     return FDM_OK;
 }
 
+// Tile every instance with `requested` rows (0: the default rule) under the
+// context's schedule; re-upload the batched tile map and invalidate the
+// device table and the cached graph.
+fdm_status retile(fdm_ctx *c, int requested)
+{
+    int64_t batch_strip_rows = 0;
+    for (int i = 0; i < c->n; ++i) batch_strip_rows += strip_rows_of(c->desc[i]);
+    int64_t tile = 0;
+    for (int i = 0; i < c->n; ++i) {
+        const fdm_transport_desc &d = c->desc[i];
+        InstDev &I = c->inst[i];
+        I.rows = pick_rows(c->batched ? batch_strip_rows : strip_rows_of(d), d.ny, requested);
+        I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
+        I.chunks = (d.ny + I.rows - 1) / I.rows;
+        I.tile_begin = tile;
+        tile += (int64_t)I.strips * I.chunks;
+    }
+    c->total_tiles = tile;
+    c->table_valid = false;
+    if (c->graph) {
+        FDM_HIP(c, hipGraphExecDestroy(c->graph));
+        c->graph = nullptr;
+    }
+    if (!c->batched) return FDM_OK;
+    if (tile >= ((int64_t)1 << 31)) return fail(c, FDM_ERR_INVALID_ARG, "too many tiles for one batched launch");
+    // the map and table buffers may still feed queued work
+    FDM_HIP(c, hipStreamSynchronize(c->stream));
+    if (tile > c->tile_capacity) {
+        if (c->d_tile_inst) FDM_HIP(c, hipFree(c->d_tile_inst));
+        c->d_tile_inst = nullptr;
+        c->tile_capacity = 0;
+        FDM_HIP(c, hipMalloc((void **)&c->d_tile_inst, sizeof(int32_t) * tile));
+        c->tile_capacity = tile;
+    }
+    if (!c->d_inst) FDM_HIP(c, hipMalloc((void **)&c->d_inst, sizeof(InstDev) * c->n));
+    if (!c->h_inst_pinned)
+        FDM_HIP(c, hipHostMalloc((void **)&c->h_inst_pinned, sizeof(InstDev) * c->n, hipHostMallocDefault));
+    std::vector<int32_t> map(tile);
+    for (int i = 0; i < c->n; ++i) {
+        const int64_t b = c->inst[i].tile_begin, e = b + (int64_t)c->inst[i].strips * c->inst[i].chunks;
+        for (int64_t t = b; t < e; ++t) map[t] = i;
+    }
+    FDM_HIP(c, hipMemcpy(c->d_tile_inst, map.data(), sizeof(int32_t) * tile, hipMemcpyHostToDevice));
+    return FDM_OK;
+}
+
 fdm_status compute_stats(fdm_ctx *c, void *const *a11, void *const *a12, fdm_stats *out)
 {
     for (int i = 0; i < c->n; ++i) {
@@ -289,8 +338,6 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     c->schedule = opt.schedule;
     c->precision = opt.precision;
     c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN;
-    int64_t batch_strip_rows = 0;
-    for (int i = 0; i < n_instances; ++i) batch_strip_rows += strip_rows_of(descs[i]);
     c->desc.assign(descs, descs + n_instances);
     c->inst.resize(n_instances);
     c->dt.resize(n_instances);
@@ -314,6 +361,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     int64_t total = 0;
     for (int i = 0; i < n_instances; ++i) total += 2 * (int64_t)descs[i].nx * descs[i].ny;
     const size_t elem = opt.precision == FDM_PRECISION_FP64 ? sizeof(double) : sizeof(float);
+    c->elem = elem;
     INIT_HIP(hipMalloc((void **)&c->workspace, elem * total));
     INIT_HIP(hipMalloc((void **)&c->d_partials, sizeof(fdm::StatsPartial) * fdm::kStatsBlocks));
     INIT_HIP(hipMalloc((void **)&c->d_stats, sizeof(double) * 5 * n_instances));
@@ -321,7 +369,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     INIT_HIP(hipMalloc((void **)&c->d_absmax, sizeof(float) * fdm::kAbsmaxBlocks));
 
     std::vector<float> absmax(fdm::kAbsmaxBlocks);
-    int64_t off = 0, tile = 0;
+    int64_t off = 0;
     for (int i = 0; i < n_instances; ++i) {
         const fdm_transport_desc &d = descs[i];
         const int64_t n = (int64_t)d.nx * d.ny;
@@ -380,27 +428,11 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         I.theta = (float)I.thetad;
         I.limiter = d.limiter;
         I.vkind = d.velocity;
-        I.rows = pick_rows(c->batched ? batch_strip_rows : strip_rows_of(d), d.ny, opt.tile_rows);
-        I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
-        I.chunks = (d.ny + I.rows - 1) / I.rows;
-        I.tile_begin = tile;
-        tile += (int64_t)I.strips * I.chunks;
     }
-    c->total_tiles = tile;
-    if (c->batched) {
-        if (tile >= ((int64_t)1 << 31)) {
-            fail(c, FDM_ERR_INVALID_ARG, "too many tiles for one batched launch");
-            return bail(FDM_ERR_INVALID_ARG);
-        }
-        std::vector<int32_t> map(tile);
-        for (int i = 0; i < n_instances; ++i) {
-            const int64_t b = c->inst[i].tile_begin, e = b + (int64_t)c->inst[i].strips * c->inst[i].chunks;
-            for (int64_t t = b; t < e; ++t) map[t] = i;
-        }
-        INIT_HIP(hipMalloc((void **)&c->d_tile_inst, sizeof(int32_t) * tile));
-        INIT_HIP(hipMemcpy(c->d_tile_inst, map.data(), sizeof(int32_t) * tile, hipMemcpyHostToDevice));
-        INIT_HIP(hipMalloc((void **)&c->d_inst, sizeof(InstDev) * n_instances));
-        INIT_HIP(hipHostMalloc((void **)&c->h_inst_pinned, sizeof(InstDev) * n_instances, hipHostMallocDefault));
+    {
+        c->requested_rows = opt.tile_rows;
+        const fdm_status ts = retile(c, opt.tile_rows);
+        if (ts != FDM_OK) return bail(ts);
     }
     INIT_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
 #undef INIT_HIP
@@ -505,6 +537,115 @@ fdm_status fdm_run(fdm_ctx *c, const fdm_loading *loading, void *const *alpha11,
     }
     if (!history) FDM_HIP(c, hipStreamSynchronize(c->stream));
     return FDM_OK;
+}
+
+int32_t fdm_tile_rows(const fdm_ctx *c, int32_t i)
+{
+    if (!c || i < 0 || i >= c->n) return -1;
+    return c->inst[i].rows;
+}
+
+fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, int32_t trial_steps,
+                        fdm_tune_trial *trials, int32_t max_trials, int32_t *n_trials)
+{
+    if (!c) return FDM_ERR_INVALID_ARG;
+    if (c->sticky) return FDM_ERR_DEVICE;
+    if (n_trials) *n_trials = 0;
+    if (trial_steps < 1) return fail(c, FDM_ERR_INVALID_ARG, "trial_steps must be >= 1");
+    if (max_trials < 0 || (max_trials > 0 && !trials))
+        return fail(c, FDM_ERR_INVALID_ARG, "trials must hold max_trials >= 0 entries");
+    fdm_status st = check_ptrs(c, alpha11, alpha12);
+    if (st != FDM_OK) return st;
+
+    // scratch copy of the state: the trials advance it, the caller's arrays stay
+    int64_t total = 0;
+    for (int i = 0; i < c->n; ++i) total += 2 * (int64_t)c->desc[i].nx * c->desc[i].ny;
+    void *scratch = nullptr;
+    {
+        const hipError_t e = hipMalloc(&scratch, c->elem * total);
+        if (e != hipSuccess)
+            return fail(c, e == hipErrorOutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    std::vector<void *> s11(c->n), s12(c->n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool was_batched = c->batched;
+    int best_rows = -1;
+    bool best_batched = was_batched;
+    double best = 0.0;
+    int32_t count = 0;
+    int max_ny = 0;
+    for (int i = 0; i < c->n; ++i) max_ny = std::max(max_ny, c->desc[i].ny);
+    std::vector<bool> schedules;
+    if (c->n > 1 && c->schedule == FDM_SCHEDULE_AUTO) schedules = {true, false};
+    else schedules = {was_batched};
+
+    auto run = [&]() -> fdm_status {
+        int64_t off = 0;
+        for (int i = 0; i < c->n; ++i) {
+            const int64_t n = (int64_t)c->desc[i].nx * c->desc[i].ny;
+            s11[i] = static_cast<char *>(scratch) + c->elem * off;
+            s12[i] = static_cast<char *>(scratch) + c->elem * (off + n);
+            off += 2 * n;
+            FDM_HIP(c, hipMemcpyAsync(s11[i], alpha11[i], c->elem * n, hipMemcpyDeviceToDevice, c->stream));
+            FDM_HIP(c, hipMemcpyAsync(s12[i], alpha12[i], c->elem * n, hipMemcpyDeviceToDevice, c->stream));
+        }
+        FDM_HIP(c, hipEventCreate(&e0));
+        FDM_HIP(c, hipEventCreate(&e1));
+        for (bool batched : schedules) {
+            for (int rows : {4, 8, 12, 16, 24, 32, 48, 64}) {
+                if (rows > max_ny && rows != 4) continue;
+                c->batched = batched;
+                fdm_status r = retile(c, rows);
+                if (r != FDM_OK) return r;
+                r = bind(c, s11.data(), s12.data());
+                if (r != FDM_OK) return r;
+                r = enqueue_steps(c, 1, c->stream);   // warm-up
+                if (r != FDM_OK) return r;
+                double t[2];
+                for (double &ti : t) {
+                    FDM_HIP(c, hipEventRecord(e0, c->stream));
+                    r = enqueue_steps(c, trial_steps, c->stream);
+                    if (r != FDM_OK) return r;
+                    FDM_HIP(c, hipEventRecord(e1, c->stream));
+                    FDM_HIP(c, hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    FDM_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+                    ti = 1e-3 * ms / trial_steps;
+                }
+                const double sec = std::min(t[0], t[1]);
+                if (count < max_trials) {
+                    trials[count].tile_rows = rows;
+                    trials[count].schedule = batched ? FDM_SCHEDULE_BATCHED : FDM_SCHEDULE_PLAIN;
+                    trials[count].seconds_per_step = sec;
+                }
+                ++count;
+                if (best_rows < 0 || sec < best) {
+                    best = sec;
+                    best_rows = rows;
+                    best_batched = batched;
+                }
+            }
+        }
+        return FDM_OK;
+    };
+    st = run();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(scratch);
+    if (st == FDM_OK && best_rows > 0) {
+        c->batched = best_batched;
+        st = retile(c, best_rows);
+        if (st == FDM_OK) c->requested_rows = best_rows;
+    } else if (!c->sticky) {
+        // restore the previous tiling after a non-device failure
+        c->batched = was_batched;
+        (void)retile(c, c->requested_rows);
+    }
+    c->table_valid = false;   // the table points at the scratch arrays
+    if (n_trials) *n_trials = std::min(count, max_trials);
+    return st;
 }
 
 double fdm_transport_dt(const fdm_ctx *c, int32_t i)

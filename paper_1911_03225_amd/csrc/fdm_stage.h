@@ -78,6 +78,16 @@ __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); 
 __device__ __forceinline__ double vabs(double a) { return fabs(a); }
 __device__ __forceinline__ double vsign(double m, double s) { return copysign(m, s); }
 
+// Multiply-add.  float: always one fused operation.  Both stage files turn
+// implicit contraction off, so every fusion is written out here and each of
+// the eight unrolled copies of the row loop rounds identically: otherwise the
+// compiler may fuse a different product in different copies, a row's Hhat
+// then depends on which copy computes it (the tile height), and the two tiles
+// that both compute a boundary row can disagree in the last bit.  double:
+// separate multiply and add, as in the definition.
+__device__ __forceinline__ float madd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double madd(double a, double b, double c) { return a * b + c; }
+
 template <typename R> struct Arith;
 
 template <> struct Arith<float> {
@@ -161,7 +171,7 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         // H = V.p: the central-upwind weights reduce to pure upwinding.
         const R px = V1 > R(0) ? pxm : pxp;
         const R py = V2 > R(0) ? pym : pyp;
-        return V1 * px + V2 * py;
+        return madd(V2, py, V1 * px);
     } else {
         // H = v0 |p| at the four corners (s,t) in {-,+}^2, dH/dp = v0 p/|p|.
         // |p|^2 is clamped below at the smallest normal number before the
@@ -169,8 +179,9 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         // still gives H = 0 and speed 0, and gradients below 1e-19 (float)
         // move with speed v0 p / 1e-19 instead of a full-speed direction.
         constexpr R kTiny = Arith<R>::tiny;
-        const R xm2 = pxm * pxm, xp2 = pxp * pxp, ym2 = pym * pym, yp2 = pyp * pyp;
-        const R r00 = xm2 + ym2, r01 = xm2 + yp2, r10 = xp2 + ym2, r11 = xp2 + yp2;
+        const R xm2 = pxm * pxm, xp2 = pxp * pxp;
+        const R r00 = madd(pym, pym, xm2), r01 = madd(pyp, pyp, xm2);
+        const R r10 = madd(pym, pym, xp2), r11 = madd(pyp, pyp, xp2);
         const R g00 = v0 * Arith<R>::rsq(vmax(r00, kTiny));
         const R g01 = v0 * Arith<R>::rsq(vmax(r01, kTiny));
         const R g10 = v0 * Arith<R>::rsq(vmax(r10, kTiny));
@@ -199,8 +210,8 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         const R wxm = ap * ia, wxp = -am * ia;
         const R wym = bp * ib, wyp = -bm * ib;
         const R visc_x = ap * am * ia, visc_y = bp * bm * ib;
-        return wxm * (wym * H00 + wyp * H01) + wxp * (wym * H10 + wyp * H11)
-             + visc_x * (pxp - pxm) + visc_y * (pyp - pym);
+        const R sum = madd(wxp, madd(wyp, H11, wym * H10), wxm * madd(wyp, H01, wym * H00));
+        return madd(visc_y, pyp - pym, madd(visc_x, pxp - pxm, sum));
     }
 }
 
@@ -429,15 +440,16 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         }
 
         // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
+        // (halving is exact, so each face value rounds once, fused or not)
         const R s0 = limited_slope<LK>(ym1, y0, yp1, theta);
-        const R pyp = -(y0 - R(0.5) * s0);
-        const R pym = -(ym1 + R(0.5) * sl[hp]);
+        const R pyp = -madd(R(-0.5), s0, y0);
+        const R pym = -madd(R(0.5), sl[hp], ym1);
         sl[h] = s0;
         // Steps 1-2 along x (alpha_12 = w_x), neighbours from adjacent lanes
         const R wl = from_left(wx), wr = from_right(wx);
         const R sx = limited_slope<LK>(wl, wx, wr, theta);
-        const R pxp = wx - R(0.5) * sx;
-        const R pxm = from_left(wx + R(0.5) * sx);
+        const R pxp = madd(R(-0.5), sx, wx);
+        const R pxm = from_left(madd(R(0.5), sx, wx));
         // Steps 2-4
         R hv;
         if constexpr (kF64)
@@ -451,15 +463,15 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         {   // x-edge (j+1/2, k): d(alpha_12)/dt = -(Hhat_{j+1} - Hhat_j)/dx; not on the extra row
             R nv;
             if constexpr (kF64) nv = wx + I.dtd * (-(hr - hv) / I.dxd);
-            else nv = wx - cx * (hr - hv);
-            if constexpr (kBase) nv = R(0.5) * b12 + R(0.5) * nv;
+            else nv = madd(-cx, hr - hv, wx);
+            if constexpr (kBase) nv = madd(R(0.5), b12, R(0.5) * nv);
             put(row_ptr<S>(d12, k, nx, it < nrows), off_st, S(nv));
         }
         {   // y-edge (j, k-1/2): d(alpha_11)/dt = (Hhat_k - Hhat_{k-1})/dy; from the second row on
             R nv;
             if constexpr (kF64) nv = ym1 + I.dtd * ((hv - hprev) / I.dyd);
-            else nv = ym1 + cy * (hv - hprev);
-            if constexpr (kBase) nv = R(0.5) * b11 + R(0.5) * nv;
+            else nv = madd(cy, hv - hprev, ym1);
+            if constexpr (kBase) nv = madd(R(0.5), b11, R(0.5) * nv);
             put(row_ptr<S>(d11, kprev, nx, it > 0), off_st, S(nv));
         }
         kprev = k;

@@ -1,5 +1,11 @@
 // fdm_stage_f32.hip -- FP32-arithmetic instances of the stage kernels
-// (float32 state).  The compiler may fuse multiply-adds here.
+// (float32 state).
+//
+// Implicit multiply-add contraction is off: the fused operations are the
+// explicit madd() calls of the stage code, the same in every unrolled copy of
+// the row loop and in every kernel instance, so results do not depend on the
+// tile height or on the batched / plain schedule.
+#pragma clang fp contract(off)
 #include "fdm_stage.h"
 
 namespace fdm {

@@ -55,6 +55,11 @@ class fdm_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class fdm_tune_trial(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("seconds_per_step", ctypes.c_double)]
+
+
 class fdm_static_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
@@ -97,6 +102,9 @@ def load_library(path: str = LIB_PATH):
     lib.fdm_run.argtypes = [vp, P(fdm_loading), fpp, fpp, i32, i32, P(fdm_stats)]
     lib.fdm_transport_dt.argtypes = [vp, i32]
     lib.fdm_transport_dt.restype = ctypes.c_double
+    lib.fdm_tile_rows.argtypes = [vp, i32]
+    lib.fdm_tile_rows.restype = i32
+    lib.fdm_autotune.argtypes = [vp, fpp, fpp, i32, P(fdm_tune_trial), i32, P(i32)]
     lib.fdm_destroy.argtypes = [vp]
     lib.fdm_destroy.restype = None
     lib.fdm_status_string.argtypes = [ctypes.c_int]
@@ -104,7 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdm_last_error.argtypes = [vp]
     lib.fdm_last_error.restype = ctypes.c_char_p
     for name in ("fdm_transport_init", "fdm_transport_step", "fdm_transport_stats",
-                 "fdm_static_solve", "fdm_run"):
+                 "fdm_static_solve", "fdm_run", "fdm_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -254,6 +262,23 @@ def fdm_static_solve(desc_, alpha11, alpha12, tau13_out, stream=None) -> None:
                                          _ptr(alpha12, None, "alpha12"), _ptr(tau13_out, None, "tau13"),
                                          _stream_handle(stream))
     _check(st, "fdm_static_solve", None)
+
+
+def fdm_tile_rows(ctx, instance: int = 0) -> int:
+    return int(load_library().fdm_tile_rows(ctx.handle, int(instance)))
+
+
+def fdm_autotune(ctx, alpha11, alpha12, trial_steps: int = 10, max_trials: int = 64):
+    """Time the candidate tilings on a copy of the state and keep the
+    fastest; returns the list of measured trials (dicts) in the order run."""
+    p11, p12 = _ptr_arrays(ctx, alpha11, alpha12)
+    arr = (fdm_tune_trial * max_trials)()
+    n = ctypes.c_int32(0)
+    _check(load_library().fdm_autotune(ctx.handle, p11, p12, int(trial_steps), arr, int(max_trials),
+                                       ctypes.byref(n)), "fdm_autotune", ctx)
+    names = {v: k for k, v in SCHEDULES.items()}
+    return [{"tile_rows": arr[i].tile_rows, "schedule": names.get(arr[i].schedule, arr[i].schedule),
+             "seconds_per_step": arr[i].seconds_per_step} for i in range(n.value)]
 
 
 def fdm_transport_dt(ctx, instance: int = 0) -> float:

@@ -50,6 +50,7 @@ def test_struct_sizes_match_c_layout(fdm):
     assert ctypes.sizeof(fdm.fdm_transport_desc) == 104
     assert ctypes.sizeof(fdm.fdm_stats) == 80
     assert ctypes.sizeof(fdm.fdm_options) == 16
+    assert ctypes.sizeof(fdm.fdm_tune_trial) == 16
 
 
 def test_status_strings(fdm):
@@ -103,6 +104,8 @@ def test_null_arguments(fdm):
     assert lib.fdm_transport_step(None, None, None, 1) == fdm.FDM_ERR_INVALID_ARG
     assert lib.fdm_run(None, None, None, None, 1, 1, None) == fdm.FDM_ERR_INVALID_ARG
     assert fdm.load_library().fdm_transport_dt(None, 0) == -1.0
+    assert lib.fdm_tile_rows(None, 0) == -1
+    assert lib.fdm_autotune(None, None, None, 1, None, 0, None) == fdm.FDM_ERR_INVALID_ARG
     lib.fdm_destroy(None)   # no-op
 
 

@@ -249,6 +249,32 @@ def test_tile_rows_bitwise(fdm):
         assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
 
 
+# Every row of a tile is computed by one of eight unrolled copies of the row
+# loop, chosen by the row's offset in its tile; a boundary row's Hhat is
+# computed by both tiles.  Results may not depend on the tile height, for
+# any limiter, velocity kind or precision (a copy that rounded differently,
+# e.g. by fusing another product, showed up only with a celerity field).
+@pytest.mark.parametrize("precision", ["fp32", "fp64_arith", "fp64"])
+@pytest.mark.parametrize("limiter,kind", [("minmod", "field"), ("superbee", "field"), ("mc", "uniform"),
+                                          ("minmod", "uniform"), ("none", "uniform"),
+                                          ("superbee", "prescribed")])
+def test_tile_rows_bitwise_all_kernels(fdm, limiter, kind, precision):
+    rng = np.random.default_rng(5)
+    nx, ny = 310, 270
+    a11, a12 = W.diagonal_bands(nx, ny, rng, n_bands=6)
+    kw = dict(limiter=limiter, cfl=0.4)
+    if kind == "field":
+        kw["v0_field"] = W.fourier_celerity(nx, ny, rng, kmax=2)
+    elif kind == "prescribed":
+        kw.update(velocity="prescribed", V=(1.0, -0.5))
+    else:
+        kw["v0"] = -1.0
+    outs = [gpu_run(a11, a12, 24, options={"tile_rows": r, "precision": precision}, **dict(kw))[1][-1]
+            for r in (1, 3, 4, 8, 12, 16, 64)]
+    for o in outs[1:]:
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+
+
 def test_deterministic(fdm):
     a11, a12, v0 = W.c3_bands(512, seed=7)
     r1 = gpu_run(a11, a12, 50, limiter="minmod", cfl=0.45, v0_field=v0)[1][-1]
