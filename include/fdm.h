@@ -173,21 +173,40 @@ fdm_status fdm_transport_step(fdm_ctx *ctx, void *const *alpha11,
 fdm_status fdm_transport_stats(fdm_ctx *ctx, void *const *alpha11,
                                void *const *alpha12, fdm_stats *out);
 
-/* Static problem (sec. 3.1.2): layer-averaged shear stress tau_13 (sec.
- * 3.2.1) of a homogeneous isotropic cell for given layer densities. */
+/* Static problem (sec. 3.1.2, homogeneous Green-operator solution) in the
+ * layer case (sec. 3.2.1): the layer-averaged shear stress tau_13 at the
+ * layer nodes for given densities.
+ *
+ * Cell: the nx-by-ny layer grid, n3 = cell_l3/dx voxels along x3 (cubic
+ * voxels, so dx == dy is required), homogeneous isotropic elasticity
+ * (mu > 0, lambda > -2 mu / 3).  The layer is h = layer_h/dx voxels thick
+ * (1 <= h <= n3, both whole numbers) and carries U^p = phi e1 (x) e3 with
+ * phi the potential of the densities (alpha_12 = D1 phi, alpha_11 = -D2 phi,
+ * forward differences) and mean phi_mean (the densities do not fix it).
+ * The mean strain is eps13 in the 13 component, zero otherwise.  Output:
+ * tau13 = mean over the layer voxels of sigma_13, whose mean over the nodes
+ * is 2 mu eps13 - mu (h/n3) phi_mean. */
 typedef struct fdm_static_desc {
     int32_t nx, ny;          /* layer grid (as in fdm_transport_desc)           */
-    double dx, dy;
+    double dx, dy;           /* node spacing, dx == dy                          */
     double mu, lambda;       /* elastic constants (dimensionless: mu = 1)       */
-    double layer_h;          /* layer thickness                                 */
-    double cell_l3;          /* cell height along x3                            */
+    double layer_h;          /* layer thickness, a whole number of voxels       */
+    double cell_l3;          /* cell height along x3, a whole number of voxels  */
     double eps13;            /* macroscopic shear strain                        */
+    double phi_mean;         /* mean of U^p_13 over the layer nodes             */
+    int32_t precision;       /* fdm_precision: FP64 = double arrays and FFTs,
+                              * otherwise float arrays and FFTs               */
+    int32_t reserved;        /* must be 0                                       */
 } fdm_static_desc;
 
-/* Writes tau13_out[k*nx + j] at the nodes.  Returns FDM_ERR_UNSUPPORTED in
- * this build. */
-fdm_status fdm_static_solve(const fdm_static_desc *desc, const float *alpha11,
-                            const float *alpha12, float *tau13_out, void *hip_stream);
+/* Writes tau13_out[k*nx + j] at the nodes.  alpha11/alpha12/tau13_out are
+ * device arrays of nx*ny floats (doubles in FP64 precision), distinct; the
+ * densities are read only.  Builds the FFT plans and the multiplier table
+ * for the call, runs on hip_stream and returns after the result is complete
+ * (synchronous).  Errors: FDM_ERR_INVALID_ARG (checked on the host first),
+ * FDM_ERR_OUT_OF_MEMORY, FDM_ERR_DEVICE (message in fdm_last_error(NULL)). */
+fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11,
+                            const void *alpha12, void *tau13_out, void *hip_stream);
 
 /* Coupled loading for fdm_run (sec. 3.1.1 alternating static/evolution
  * split); reserved. */
@@ -221,7 +240,7 @@ int32_t fdm_tile_rows(const fdm_ctx *ctx, int32_t instance);
 typedef struct fdm_tune_trial {
     int32_t tile_rows;       /* rows per wave tile tried (all instances)        */
     int32_t schedule;        /* FDM_SCHEDULE_BATCHED or FDM_SCHEDULE_PLAIN      */
-    double seconds_per_step; /* median of two timed runs of trial_steps steps   */
+    double seconds_per_step; /* faster of two timed runs of trial_steps steps   */
 } fdm_tune_trial;
 
 /* Autotuner for the launch shape (not a step of the paper's method: tiling

@@ -14,7 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdm.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
-           ("fdm_kernels.hip", "fdm_stage_f32.hip", "fdm_stage_f64.hip", "fdm_api.hip")]
+           ("fdm_kernels.hip", "fdm_stage_f32.hip", "fdm_stage_f64.hip", "fdm_static.hip", "fdm_api.hip")]
+# rocFFT for the static solve's transforms
+LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = "gfx950"
 
 
@@ -38,7 +40,7 @@ def flags():
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + SOURCES + ["-o", tmp]
+    cmd = [hipcc()] + flags() + SOURCES + LIBS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

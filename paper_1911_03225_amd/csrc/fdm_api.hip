@@ -17,6 +17,7 @@
 
 #include "../../include/fdm.h"
 #include "fdm_internal.h"
+#include "fdm_static.h"
 
 using fdm::InstDev;
 
@@ -101,6 +102,42 @@ std::string check_desc(const fdm_transport_desc &d)
     if (d.velocity == FDM_VELOCITY_PRESCRIBED && !(std::isfinite(d.V[0]) && std::isfinite(d.V[1])))
         return "V must be finite";
     return "";
+}
+
+// A whole number of voxels: v / d within 1e-9 of an integer >= 1.
+bool whole_voxels(double v, double d, int *out)
+{
+    if (!(std::isfinite(v) && v > 0.0)) return false;
+    const double r = v / d, k = std::round(r);
+    if (!(k >= 1.0 && k < 2147483647.0) || std::fabs(r - k) > 1e-9 * k) return false;
+    *out = (int)k;
+    return true;
+}
+
+// Host-side validation of a static descriptor; fills the internal parameters.
+std::string check_static(const fdm_static_desc &d, fdm::StaticParams *q)
+{
+    if (d.nx < 1 || d.ny < 1) return "nx and ny must be >= 1";
+    if ((int64_t)d.nx * d.ny >= (int64_t)1 << 31) return "nx*ny must be < 2^31";
+    if (!finite_pos(d.dx) || !finite_pos(d.dy)) return "dx and dy must be finite and > 0";
+    if (d.dx != d.dy) return "dx must equal dy (cubic voxels)";
+    if (!finite_pos(d.mu)) return "mu must be finite and > 0";
+    if (!(std::isfinite(d.lambda) && 3.0 * d.lambda + 2.0 * d.mu > 0.0))
+        return "lambda must be finite with 3 lambda + 2 mu > 0";
+    int h = 0, n3 = 0;
+    if (!whole_voxels(d.layer_h, d.dx, &h)) return "layer_h must be a whole number (>= 1) of voxels of size dx";
+    if (!whole_voxels(d.cell_l3, d.dx, &n3)) return "cell_l3 must be a whole number (>= 1) of voxels of size dx";
+    if (h > n3) return "layer_h must not exceed cell_l3";
+    if (!std::isfinite(d.eps13) || !std::isfinite(d.phi_mean)) return "eps13 and phi_mean must be finite";
+    if (d.precision < FDM_PRECISION_FP32 || d.precision > FDM_PRECISION_FP64) return "unknown precision";
+    if (d.reserved != 0) return "reserved must be 0";
+    *q = fdm::StaticParams{d.nx, d.ny, d.dx, d.dy, d.mu, d.lambda, h, n3, d.precision == FDM_PRECISION_FP64};
+    return "";
+}
+
+double static_mean_stress(const fdm_static_desc &d, const fdm::StaticParams &q)
+{
+    return 2.0 * d.mu * d.eps13 - d.mu * d.phi_mean * (double)q.h / (double)q.n3;
 }
 
 // Largest float not above x (x > 0).
@@ -466,16 +503,32 @@ fdm_status fdm_transport_stats(fdm_ctx *c, void *const *alpha11, void *const *al
     return compute_stats(c, alpha11, alpha12, out);
 }
 
-fdm_status fdm_static_solve(const fdm_static_desc *desc, const float *alpha11, const float *alpha12,
-                            float *tau13_out, void *hip_stream)
+fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11, const void *alpha12,
+                            void *tau13_out, void *hip_stream)
 {
-    (void)desc;
-    (void)alpha11;
-    (void)alpha12;
-    (void)tau13_out;
-    (void)hip_stream;
-    g_init_error = "the static FFT solve is not available in this build";
-    return FDM_ERR_UNSUPPORTED;
+    if (!desc) return fail(nullptr, FDM_ERR_INVALID_ARG, "desc must not be NULL");
+    fdm::StaticParams q;
+    const std::string m = check_static(*desc, &q);
+    if (!m.empty()) return fail(nullptr, FDM_ERR_INVALID_ARG, m);
+    if (!alpha11 || !alpha12 || !tau13_out)
+        return fail(nullptr, FDM_ERR_INVALID_ARG, "alpha11, alpha12 and tau13_out must not be NULL");
+    if (alpha11 == alpha12 || tau13_out == alpha11 || tau13_out == alpha12)
+        return fail(nullptr, FDM_ERR_INVALID_ARG, "alpha11, alpha12 and tau13_out must be distinct");
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::string err;
+    fdm::StaticPlan *plan = nullptr;
+    fdm::StaticStatus st = fdm::static_plan_create(q, s, &plan, err);
+    if (st == fdm::StaticStatus::Ok) {
+        st = fdm::static_plan_run(plan, alpha11, alpha12, tau13_out, static_mean_stress(*desc, q), s, err);
+        const hipError_t e = hipStreamSynchronize(s);
+        if (st == fdm::StaticStatus::Ok && e != hipSuccess) {
+            st = fdm::StaticStatus::Device;
+            err = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
+        }
+    }
+    fdm::static_plan_destroy(plan);
+    if (st == fdm::StaticStatus::Ok) return FDM_OK;
+    return fail(nullptr, st == fdm::StaticStatus::OutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE, err);
 }
 
 fdm_status fdm_run(fdm_ctx *c, const fdm_loading *loading, void *const *alpha11, void *const *alpha12,

@@ -65,7 +65,8 @@ class fdm_static_desc(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("layer_h", ctypes.c_double), ("cell_l3", ctypes.c_double),
-                ("eps13", ctypes.c_double)]
+                ("eps13", ctypes.c_double), ("phi_mean", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class fdm_loading(ctypes.Structure):
@@ -257,11 +258,26 @@ def fdm_run(ctx, alpha11, alpha12, n_steps: int, chunk: int, loading=None, histo
     return [[hist[c * ctx.n + i].as_dict() for i in range(ctx.n)] for c in range(n_chunks)]
 
 
-def fdm_static_solve(desc_, alpha11, alpha12, tau13_out, stream=None) -> None:
-    st = load_library().fdm_static_solve(ctypes.byref(desc_), _ptr(alpha11, None, "alpha11"),
-                                         _ptr(alpha12, None, "alpha12"), _ptr(tau13_out, None, "tau13"),
-                                         _stream_handle(stream))
+def static_desc(nx: int, ny: int, dx: float = 1.0, dy: float = None, mu: float = 1.0, lam: float = 1.5,
+                layer_h: float = 4.0, cell_l3: float = 512.0, eps13: float = 0.0, phi_mean: float = 0.0,
+                precision="fp32") -> fdm_static_desc:
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return fdm_static_desc(int(nx), int(ny), float(dx), float(dx if dy is None else dy), float(mu), float(lam),
+                           float(layer_h), float(cell_l3), float(eps13), float(phi_mean), p, 0)
+
+
+def fdm_static_solve(desc_, alpha11, alpha12, tau13_out=None, stream=None):
+    """tau13 (layer-averaged shear stress at the nodes) for the densities;
+    allocates tau13_out when not given.  Synchronous."""
+    dtype = torch.float64 if desc_.precision == PRECISIONS["fp64"] else torch.float32
+    shape = (desc_.ny, desc_.nx)
+    if tau13_out is None:
+        tau13_out = torch.empty(shape, dtype=dtype, device=alpha11.device)
+    st = load_library().fdm_static_solve(ctypes.byref(desc_), _ptr(alpha11, shape, "alpha11", dtype),
+                                         _ptr(alpha12, shape, "alpha12", dtype),
+                                         _ptr(tau13_out, shape, "tau13_out", dtype), _stream_handle(stream))
     _check(st, "fdm_static_solve", None)
+    return tau13_out
 
 
 def fdm_tile_rows(ctx, instance: int = 0) -> int:

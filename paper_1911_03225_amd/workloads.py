@@ -96,6 +96,30 @@ def ring(nx: int, ny: int, R: float, sigma: float, A: float = 1.0,
     return densities_from_phi(phi, dx, dx)
 
 
+def plateau_rings(nx: int, ny: int, seed: int = 4, count: int = 20, rmin: float = 20.0, rmax: float = 80.0,
+                  plateau: float = 0.2, sigma: float = 2.0, dx: float = 1.0):
+    """Seeded loops for the coupled workload: phi = sum over loops of
+    +-plateau * erfc((r - R)/(sigma sqrt2)) / 2 (a plateau inside each loop,
+    erfc edges, periodic images), centres uniform, radii uniform in
+    [rmin, rmax], signs random.  Returns (phi, alpha11, alpha12): phi float64
+    at the nodes, the densities float32."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly = nx * dx, ny * dx
+    X, Y = np.meshgrid(np.arange(nx) * dx, np.arange(ny) * dx, indexing="xy")
+    phi = np.zeros((ny, nx))
+    for _ in range(count):
+        cx, cy = rng.uniform(0, Lx), rng.uniform(0, Ly)
+        R = rng.uniform(rmin, rmax)
+        A = plateau * rng.choice([-1.0, 1.0])
+        for mx in (-1, 0, 1):
+            for my in (-1, 0, 1):
+                z = (np.hypot(X - cx - mx * Lx, Y - cy - my * Ly) - R) / (sigma * sqrt(2.0))
+                close = z < 30.0
+                phi[close] += 0.5 * A * _verfc(z[close])
+    a11, a12 = densities_from_phi(phi, dx, dx)
+    return phi, a11, a12
+
+
 def ring_phi_profile(r, R: float, sigma: float, A: float = 1.0):
     """The radial plateau Phi(r) used by ``ring`` (for exact solutions)."""
     r = np.asarray(r, dtype=np.float64)

@@ -51,6 +51,7 @@ def test_struct_sizes_match_c_layout(fdm):
     assert ctypes.sizeof(fdm.fdm_stats) == 80
     assert ctypes.sizeof(fdm.fdm_options) == 16
     assert ctypes.sizeof(fdm.fdm_tune_trial) == 16
+    assert ctypes.sizeof(fdm.fdm_static_desc) == 80
 
 
 def test_status_strings(fdm):
@@ -109,11 +110,44 @@ def test_null_arguments(fdm):
     lib.fdm_destroy(None)   # no-op
 
 
-def test_static_solve_reports_unsupported(fdm):
+STATIC_BAD = [
+    (dict(nx=0), "nx and ny"),
+    (dict(dx=1.0, dy=0.5), "dx must equal dy"),
+    (dict(mu=0.0), "mu"),
+    (dict(lam=-1.0), "lambda"),
+    (dict(layer_h=2.5), "layer_h"),
+    (dict(layer_h=0.0), "layer_h"),
+    (dict(cell_l3=3.0, layer_h=4.0), "must not exceed"),
+    (dict(cell_l3=float("inf")), "cell_l3"),
+    (dict(eps13=float("nan")), "eps13"),
+    (dict(precision=5), "precision"),
+]
+
+
+@pytest.mark.parametrize("kw,msg", STATIC_BAD)
+def test_static_solve_rejects_bad_descriptors_on_host(fdm, kw, msg):
     import ctypes
     lib = fdm.load_library()
-    d = fdm.fdm_static_desc()
-    assert lib.fdm_static_solve(ctypes.byref(d), None, None, None, None) == fdm.FDM_ERR_UNSUPPORTED
+    args = dict(nx=16, ny=16, cell_l3=16.0)
+    args.update(kw)
+    d = fdm.static_desc(**args)
+    assert lib.fdm_static_solve(ctypes.byref(d), None, None, None, None) == fdm.FDM_ERR_INVALID_ARG
+    assert msg in fdm.fdm_last_error(None)
+
+
+def test_static_solve_null_and_aliased_arrays(fdm):
+    import ctypes
+    lib = fdm.load_library()
+    d = fdm.static_desc(16, 16, cell_l3=16.0)
+    assert lib.fdm_static_solve(None, None, None, None, None) == fdm.FDM_ERR_INVALID_ARG
+    assert lib.fdm_static_solve(ctypes.byref(d), None, None, None, None) == fdm.FDM_ERR_INVALID_ARG
+    assert "NULL" in fdm.fdm_last_error(None)
+    p = ctypes.c_void_p(4096)
+    assert lib.fdm_static_solve(ctypes.byref(d), p, p, ctypes.c_void_p(8192), None) == fdm.FDM_ERR_INVALID_ARG
+    assert "distinct" in fdm.fdm_last_error(None)
+    d.reserved = 1
+    assert lib.fdm_static_solve(ctypes.byref(d), p, ctypes.c_void_p(8), ctypes.c_void_p(16), None) == \
+        fdm.FDM_ERR_INVALID_ARG
 
 
 def test_valid_descriptor_without_gpu_fails_cleanly(fdm):
