@@ -136,8 +136,8 @@ typedef struct fdm_options {
 /* Per-instance diagnostics (FP64, deterministic: fixed-order compensated
  * reductions). */
 typedef struct fdm_stats {
-    double t;                /* simulated time: step * dt                       */
-    double dt;               /* the float32 step actually used                  */
+    double t;                /* simulated time: the sum of the steps taken      */
+    double dt;               /* the float32 step last used                      */
     int64_t step;            /* steps taken since init                          */
     double sum11, sum12;     /* sum over edges of alpha_11, alpha_12            */
     double sum_abs;          /* sum over edges of |alpha_11| + |alpha_12|       */
@@ -145,6 +145,11 @@ typedef struct fdm_stats {
     double drift11, drift12; /* sum11, sum12 minus their values at the first
                                 stats evaluation of this context                */
     int64_t nonfinite;       /* number of index pairs with a NaN or Inf         */
+    /* coupled runs (fdm_run with a loading); 0 otherwise */
+    double eps13;            /* macroscopic shear strain                        */
+    double sigma13;          /* macroscopic shear stress = mean of tau13        */
+    double phi_mean;         /* mean of U^p_13 over the layer nodes             */
+    double vmax;             /* max |v0| of the last step                       */
 } fdm_stats;
 
 typedef struct fdm_ctx fdm_ctx;
@@ -208,14 +213,31 @@ typedef struct fdm_static_desc {
 fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11,
                             const void *alpha12, void *tau13_out, void *hip_stream);
 
-/* Coupled loading for fdm_run (sec. 3.1.1 alternating static/evolution
- * split); reserved. */
+/* Coupled run (sec. 3.1.1: the static problem solved with the current
+ * plastic distortion, then the transport with the new stress; sec. 3.2.1
+ * layer case).  Every step:
+ *   1. tau13 = fdm_static_solve of the current densities with the current
+ *      eps13 and phi_mean (elastic constants, layer_h, cell_l3 below; the
+ *      descriptor's dx == dy);
+ *   2. celerity v0 = -S(tau13) * mobility at the nodes, S the soft threshold
+ *      S(t) = sign(t) max(|t| - tau0, 0) (a threshold law in place of the
+ *      paper's lattice-friction energy; v0 < 0 moves fronts so as to raise
+ *      U^p_13 where tau13 > tau0), stored as float32;
+ *   3. dt = the largest float <= min(cfl min(dx,dy) / max|v0|, dt_max)
+ *      (dt_max when v0 = 0), cfl from the descriptor;
+ *   4. one transport step (Heun or Euler, time_order) with v0 frozen;
+ *   5. phi_mean -= dt * mean Hhat (Heun: the mean of the two stages' means),
+ *      eps13 += strain_rate13 * dt.
+ * eps13 and phi_mean give the state at the start of the call; the stats
+ * records report it after each chunk. */
 typedef struct fdm_loading {
     double strain_rate13;    /* macroscopic shear strain rate                   */
-    double tau0;             /* threshold stress                                */
-    double mobility;         /* 1 / eta (dimensionless)                         */
-    double mu, lambda, layer_h, cell_l3;
-    double dt_max;           /* upper bound on the adaptive step                */
+    double tau0;             /* threshold stress, >= 0                          */
+    double mobility;         /* 1 / eta (dimensionless), >= 0                   */
+    double mu, lambda, layer_h, cell_l3;   /* as in fdm_static_desc           */
+    double dt_max;           /* upper bound on the adaptive step, > 0           */
+    double eps13;            /* macroscopic shear strain at the start           */
+    double phi_mean;         /* mean of U^p_13 over the layer nodes at start    */
 } fdm_loading;
 
 /* Run n_steps in chunks of `chunk` steps (the last chunk may be shorter).
@@ -224,7 +246,13 @@ typedef struct fdm_loading {
  * (history needs ceil(n_steps/chunk) * n_instances records, instance-major
  * within a chunk).  history may be NULL.  Synchronizes the stream once per
  * chunk when history is given, once at the end otherwise.
- * loading != NULL (coupled) returns FDM_ERR_UNSUPPORTED in this build. */
+ * loading != NULL: the coupled run above, for a context of one instance
+ * with the LAW velocity and a CFL-controlled step (dt = 0 in its
+ * descriptor) and dx == dy; the descriptor's v0 / v0_field are not used
+ * during the run (they are again after it).  Each step synchronizes twice
+ * (for max |v0| and for the sums of Hhat); the first call allocates the
+ * coupled workspace (FFT plans, a stress and a celerity field, per-tile
+ * sums), kept until fdm_destroy. */
 fdm_status fdm_run(fdm_ctx *ctx, const fdm_loading *loading, void *const *alpha11,
                    void *const *alpha12, int32_t n_steps, int32_t chunk,
                    fdm_stats *history);

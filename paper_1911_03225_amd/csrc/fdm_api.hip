@@ -49,6 +49,19 @@ struct fdm_ctx {
     hipGraphExec_t graph = nullptr;
     int32_t graph_steps = 0;
     std::vector<void *> graph_a11, graph_a12;
+    std::vector<double> t_acc;              // simulated time per instance
+    std::vector<float> dt_last;             // step last used per instance
+    // coupled runs (single instance)
+    struct {
+        fdm::StaticPlan *plan = nullptr;
+        fdm::StaticParams q{};
+        void *tau = nullptr;                // nx*ny, state type
+        float *v0 = nullptr;                // nx*ny celerity of the run
+        double *d_hsum = nullptr;           // per-tile sums of Hhat, two stages
+        double *h_hsum = nullptr;           // pinned copy
+        int64_t cap = 0;                    // tiles per stage the sums hold
+        double eps13 = 0.0, sigma13 = 0.0, phi_mean = 0.0, vmax = 0.0;
+    } cw;
     size_t elem = sizeof(float);            // bytes per state value
     int64_t tile_capacity = 0;              // entries of d_tile_inst
     int32_t requested_rows = 0;             // tile rows asked for (0: default rule)
@@ -185,6 +198,11 @@ void release(fdm_ctx *c)
     if (c->h_stats) (void)hipHostFree(c->h_stats);
     if (c->h_inst_pinned) (void)hipHostFree(c->h_inst_pinned);
     if (c->capture) (void)hipStreamDestroy(c->capture);
+    fdm::static_plan_destroy(c->cw.plan);
+    if (c->cw.tau) (void)hipFree(c->cw.tau);
+    if (c->cw.v0) (void)hipFree(c->cw.v0);
+    if (c->cw.d_hsum) (void)hipFree(c->cw.d_hsum);
+    if (c->cw.h_hsum) (void)hipHostFree(c->cw.h_hsum);
     delete c;
 }
 
@@ -300,6 +318,16 @@ fdm_status retile(fdm_ctx *c, int requested)
     return FDM_OK;
 }
 
+// Bookkeeping of n uncoupled steps.
+void advance(fdm_ctx *c, int32_t n)
+{
+    c->steps += n;
+    for (int i = 0; i < c->n; ++i) {
+        c->t_acc[i] += (double)n * (double)c->dt[i];
+        c->dt_last[i] = c->dt[i];
+    }
+}
+
 fdm_status compute_stats(fdm_ctx *c, void *const *a11, void *const *a12, fdm_stats *out)
 {
     for (int i = 0; i < c->n; ++i) {
@@ -322,9 +350,13 @@ fdm_status compute_stats(fdm_ctx *c, void *const *a11, void *const *a12, fdm_sta
     for (int i = 0; i < c->n; ++i) {
         const double *h = c->h_stats + 5 * i;
         fdm_stats &o = out[i];
-        o.dt = c->dt[i];
+        o.dt = c->dt_last[i];
         o.step = c->steps;
-        o.t = (double)c->steps * (double)c->dt[i];
+        o.t = c->t_acc[i];
+        o.eps13 = c->cw.eps13;
+        o.sigma13 = c->cw.sigma13;
+        o.phi_mean = c->cw.phi_mean;
+        o.vmax = c->cw.vmax;
         o.sum11 = h[0];
         o.sum12 = h[1];
         o.sum_abs = h[2];
@@ -335,6 +367,142 @@ fdm_status compute_stats(fdm_ctx *c, void *const *a11, void *const *a12, fdm_sta
         bad |= o.nonfinite != 0;
     }
     if (bad) return fail(c, FDM_ERR_NONFINITE, "non-finite density values found");
+    return FDM_OK;
+}
+
+// Kahan-Babuska (Neumaier) sum of n doubles in index order.
+double ordered_sum(const double *v, int64_t n)
+{
+    double s = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double t = s + v[i];
+        comp += std::fabs(s) >= std::fabs(v[i]) ? (s - t) + v[i] : (v[i] - t) + s;
+        s = t;
+    }
+    return s + comp;
+}
+
+fdm_status static_fail(fdm_ctx *c, fdm::StaticStatus st, const std::string &err)
+{
+    return fail(c, st == fdm::StaticStatus::OutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE, err);
+}
+
+// The coupled run of one instance (see fdm_loading in include/fdm.h).
+fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void *const *a12, int32_t n_steps,
+                       int32_t chunk, fdm_stats *history)
+{
+    if (c->n != 1) return fail(c, FDM_ERR_INVALID_ARG, "coupled runs need a context of one instance");
+    const fdm_transport_desc &d = c->desc[0];
+    if (d.velocity != FDM_VELOCITY_LAW) return fail(c, FDM_ERR_INVALID_ARG, "coupled runs need the LAW velocity");
+    if (d.dt != 0.0) return fail(c, FDM_ERR_INVALID_ARG, "coupled runs need a CFL-controlled step (dt = 0)");
+    if (!(std::isfinite(L.strain_rate13) && std::isfinite(L.tau0) && L.tau0 >= 0.0 && std::isfinite(L.mobility) &&
+          L.mobility >= 0.0))
+        return fail(c, FDM_ERR_INVALID_ARG, "strain_rate13 must be finite, tau0 and mobility finite and >= 0");
+    if (!finite_pos(L.dt_max)) return fail(c, FDM_ERR_INVALID_ARG, "dt_max must be finite and > 0");
+    fdm_static_desc sd{d.nx, d.ny, d.dx, d.dy, L.mu, L.lambda, L.layer_h, L.cell_l3, L.eps13, L.phi_mean,
+                       c->precision, 0};
+    fdm::StaticParams q;
+    const std::string m = check_static(sd, &q);
+    if (!m.empty()) return fail(c, FDM_ERR_INVALID_ARG, "loading: " + m);
+    fdm_status st = check_ptrs(c, a11, a12);
+    if (st != FDM_OK) return st;
+    if (n_steps == 0) return FDM_OK;
+    st = bind(c, a11, a12);
+    if (st != FDM_OK) return st;
+
+    // workspace (kept for later calls; the plan is rebuilt when the cell changes)
+    auto &w = c->cw;
+    const int64_t n = (int64_t)d.nx * d.ny;
+    const bool f64 = c->precision == FDM_PRECISION_FP64;
+    const bool same = w.plan && w.q.nx == q.nx && w.q.ny == q.ny && w.q.dx == q.dx && w.q.mu == q.mu &&
+                      w.q.lambda == q.lambda && w.q.h == q.h && w.q.n3 == q.n3 && w.q.f64 == q.f64;
+    std::string err;
+    if (!same) {
+        fdm::static_plan_destroy(w.plan);
+        w.plan = nullptr;
+        const fdm::StaticStatus ss = fdm::static_plan_create(q, c->stream, &w.plan, err);
+        if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
+        w.q = q;
+    }
+    if (!w.tau) FDM_HIP(c, hipMalloc(&w.tau, (f64 ? sizeof(double) : sizeof(float)) * n));
+    if (!w.v0) FDM_HIP(c, hipMalloc((void **)&w.v0, sizeof(float) * n));
+    InstDev I = c->inst[0];
+    const int64_t tiles = (int64_t)I.strips * I.chunks;
+    if (tiles > w.cap) {
+        if (w.d_hsum) FDM_HIP(c, hipFree(w.d_hsum));
+        if (w.h_hsum) FDM_HIP(c, hipHostFree(w.h_hsum));
+        w.d_hsum = nullptr;
+        w.h_hsum = nullptr;
+        w.cap = 0;
+        FDM_HIP(c, hipMalloc((void **)&w.d_hsum, sizeof(double) * 2 * tiles));
+        FDM_HIP(c, hipHostMalloc((void **)&w.h_hsum, sizeof(double) * 2 * tiles, hipHostMallocDefault));
+        w.cap = tiles;
+    }
+
+    const double h = std::min(d.dx, d.dy), mu = L.mu, frac = (double)q.h / (double)q.n3;
+    double eps = L.eps13, phi = L.phi_mean;
+    w.eps13 = eps;
+    w.phi_mean = phi;
+    w.sigma13 = 2.0 * mu * eps - mu * frac * phi;
+    std::vector<float> absmax(fdm::kAbsmaxBlocks);
+    const int stages = c->time_order == 2 ? 2 : 1;
+    int32_t rec = 0;
+    for (int32_t step = 0; step < n_steps; ++step) {
+        // 1-2. stress of the current state, then the celerity field
+        const double sbar = 2.0 * mu * eps - mu * frac * phi;
+        fdm::StaticStatus ss = fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, sbar, c->stream, err);
+        if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
+        ss = fdm::velocity_law(w.tau, f64, w.v0, n, L.tau0, L.mobility, c->stream, err);
+        if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
+        // 3. adaptive step
+        FDM_HIP(c, fdm::launch_absmax(w.v0, n, c->d_absmax, c->stream));
+        FDM_HIP(c, hipMemcpyAsync(absmax.data(), c->d_absmax, sizeof(float) * fdm::kAbsmaxBlocks,
+                                  hipMemcpyDeviceToHost, c->stream));
+        FDM_HIP(c, hipStreamSynchronize(c->stream));
+        float vmax = 0.0f;
+        for (float v : absmax) {
+            if (std::isnan(v)) return fail(c, FDM_ERR_NONFINITE, "non-finite celerity in the coupled run");
+            vmax = std::max(vmax, v);
+        }
+        const double bound = vmax > 0.0f ? std::min(d.cfl * h / (double)vmax, L.dt_max) : L.dt_max;
+        const float dt = round_down_float(bound);
+        // 4. one transport step with v0 frozen, per-tile sums of Hhat
+        I.v0f = w.v0;
+        I.dtd = (double)dt;
+        I.cxd = (double)dt / d.dx;
+        I.cyd = (double)dt / d.dy;
+        I.cx = (float)I.cxd;
+        I.cy = (float)I.cyd;
+        I.hsum = w.d_hsum;
+        FDM_HIP(c, fdm::launch_stage(I, fdm::MODE_FWD, c->precision, c->stream));
+        if (stages == 2) {
+            I.hsum = w.d_hsum + tiles;
+            FDM_HIP(c, fdm::launch_stage(I, fdm::MODE_HEUN2, c->precision, c->stream));
+        } else {
+            FDM_HIP(c, fdm::launch_copy(I.a11, I.w11, n, c->precision, c->stream));
+            FDM_HIP(c, fdm::launch_copy(I.a12, I.w12, n, c->precision, c->stream));
+        }
+        FDM_HIP(c, hipMemcpyAsync(w.h_hsum, w.d_hsum, sizeof(double) * stages * tiles, hipMemcpyDeviceToHost,
+                                  c->stream));
+        FDM_HIP(c, hipStreamSynchronize(c->stream));
+        // 5. mean plastic slip and loading
+        double hmean = ordered_sum(w.h_hsum, tiles) / (double)n;
+        if (stages == 2) hmean = 0.5 * (hmean + ordered_sum(w.h_hsum + tiles, tiles) / (double)n);
+        phi -= (double)dt * hmean;
+        eps += L.strain_rate13 * (double)dt;
+        c->steps += 1;
+        c->t_acc[0] += (double)dt;
+        c->dt_last[0] = dt;
+        w.eps13 = eps;
+        w.phi_mean = phi;
+        w.sigma13 = 2.0 * mu * eps - mu * frac * phi;
+        w.vmax = vmax;
+        if (history && ((step + 1) % chunk == 0 || step + 1 == n_steps)) {
+            st = compute_stats(c, a11, a12, history + rec);
+            if (st != FDM_OK) return st;
+            ++rec;
+        }
+    }
     return FDM_OK;
 }
 
@@ -378,6 +546,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     c->desc.assign(descs, descs + n_instances);
     c->inst.resize(n_instances);
     c->dt.resize(n_instances);
+    c->t_acc.assign(n_instances, 0.0);
 
     auto bail = [&](fdm_status st) {
         g_init_error = c->err;
@@ -466,6 +635,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         I.limiter = d.limiter;
         I.vkind = d.velocity;
     }
+    c->dt_last = c->dt;
     {
         c->requested_rows = opt.tile_rows;
         const fdm_status ts = retile(c, opt.tile_rows);
@@ -489,7 +659,7 @@ fdm_status fdm_transport_step(fdm_ctx *c, void *const *alpha11, void *const *alp
     if (st != FDM_OK) return st;
     st = enqueue_steps(c, n_steps, c->stream);
     if (st != FDM_OK) return st;
-    c->steps += n_steps;
+    advance(c, n_steps);
     return FDM_OK;
 }
 
@@ -536,8 +706,8 @@ fdm_status fdm_run(fdm_ctx *c, const fdm_loading *loading, void *const *alpha11,
 {
     if (!c) return FDM_ERR_INVALID_ARG;
     if (c->sticky) return FDM_ERR_DEVICE;
-    if (loading) return fail(c, FDM_ERR_UNSUPPORTED, "coupled runs are not available in this build");
     if (n_steps < 0 || chunk < 1) return fail(c, FDM_ERR_INVALID_ARG, "need n_steps >= 0 and chunk >= 1");
+    if (loading) return coupled_run(c, *loading, alpha11, alpha12, n_steps, chunk, history);
     fdm_status st = check_ptrs(c, alpha11, alpha12);
     if (st != FDM_OK) return st;
     if (n_steps == 0) return FDM_OK;
@@ -581,7 +751,7 @@ fdm_status fdm_run(fdm_ctx *c, const fdm_loading *loading, void *const *alpha11,
             if (st != FDM_OK) return st;
         }
         done += m;
-        c->steps += m;
+        advance(c, m);
         if (history) {
             st = compute_stats(c, alpha11, alpha12, history + (int64_t)rec * c->n);
             if (st != FDM_OK) return st;

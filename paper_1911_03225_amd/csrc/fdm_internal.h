@@ -48,6 +48,7 @@ struct InstDev {
     int64_t tile_begin;      // first global tile of this instance (batched)
     double cxd, cyd, thetad; // the same coefficients for FP64 arithmetic
     double dtd, dxd, dyd;    // step and spacings (FP64 update in definition form)
+    double *hsum;            // per-tile sums of Hhat (coupled runs) or nullptr
 };
 
 // Per-block partial of the diagnostics reduction (compensated sums).

@@ -348,7 +348,7 @@ template <int P> struct Phase {
 // sits in a ring slot fixed by the row number, so no copies rotate it.
 constexpr int kAhead = 2;
 
-template <typename R, typename S, int LK, int VK, bool FIELD, int MODE>
+template <typename R, typename S, int LK, int VK, bool FIELD, int MODE, bool HSUM = false>
 __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
 {
     constexpr bool kF64 = sizeof(R) == 8;
@@ -380,6 +380,7 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     S y[8], wx_[4], b12_[4], b11_[4];
     float v0_[4];
     R sl[2], hh[2];
+    R hacc = R(0);   // HSUM: this lane's sum of Hhat over the tile's own rows
     for (int j = 0; j < 4; ++j) {
         v0_[j] = 0.0f;
         b12_[j] = b11_[j] = S(0);
@@ -459,6 +460,7 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         const R hr = from_right(hv);
         const R hprev = hh[hp];
         hh[h] = hv;
+        if constexpr (HSUM) hacc += (out_col && it < nrows) ? hv : R(0);
 
         {   // x-edge (j+1/2, k): d(alpha_12)/dt = -(Hhat_{j+1} - Hhat_j)/dx; not on the extra row
             R nv;
@@ -497,6 +499,13 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         body(it + 7, Phase<7>{});
         if (it + 8 > nrows) break;
     }
+    if constexpr (HSUM) {
+        // fixed-order wave reduction in FP64, one partial per tile
+        double v = (double)hacc;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) I.hsum[(int64_t)chunk * I.strips + strip] = v;
+    }
 }
 
 // Tiles are numbered row band first (tile = chunk * strips + strip), so
@@ -513,13 +522,13 @@ __device__ __forceinline__ int64_t xcd_tile(int blocks_per_xcd)
     return logical * kWavesPerBlock + wave;
 }
 
-template <typename R, typename S, int LK, int VK, bool FIELD, int MODE>
+template <typename R, typename S, int LK, int VK, bool FIELD, int MODE, bool HSUM = false>
 __global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd)
 {
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
     const int t = (int)tile;
-    run_tile<R, S, LK, VK, FIELD, MODE>(I, t % I.strips, t / I.strips, threadIdx.x & 63);
+    run_tile<R, S, LK, VK, FIELD, MODE, HSUM>(I, t % I.strips, t / I.strips, threadIdx.x & 63);
 }
 
 // Batched: one launch for every tile of every instance; tile_inst maps a
@@ -552,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__
     }
 }
 
-template <typename R, typename S, int LK, int VK, bool FIELD>
+template <typename R, typename S, int LK, int VK, bool FIELD, bool HSUM = false>
 hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
 {
     const int64_t tiles = (int64_t)I.strips * I.chunks;
@@ -560,11 +569,12 @@ hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
     if (mode == MODE_FWD)
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_FWD>), grid, block, 0, s, I, tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_FWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd);
     else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_BWD>), grid, block, 0, s, I, tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_BWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd);
     else
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_HEUN2>), grid, block, 0, s, I, tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_HEUN2, HSUM>), grid, block, 0, s, I, tiles,
+                           per_xcd);
     return hipGetLastError();
 }
 
@@ -576,6 +586,11 @@ hipError_t launch_stage_r(const InstDev &I, int mode, hipStream_t s)
         if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_PRESCRIBED, false>(I, mode, s);
         if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_PRESCRIBED, false>(I, mode, s);
         return launch_stage_t<R, S, LK_THETA, VK_PRESCRIBED, false>(I, mode, s);
+    }
+    if (I.v0f != nullptr && I.hsum != nullptr) {   // coupled runs: also the per-tile sums of Hhat
+        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW, true, true>(I, mode, s);
+        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW, true, true>(I, mode, s);
+        return launch_stage_t<R, S, LK_THETA, VK_LAW, true, true>(I, mode, s);
     }
     if (I.v0f != nullptr) {
         if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW, true>(I, mode, s);

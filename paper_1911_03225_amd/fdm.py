@@ -49,6 +49,8 @@ class fdm_stats(ctypes.Structure):
         ("sum_abs", ctypes.c_double), ("max_norm", ctypes.c_double),
         ("drift11", ctypes.c_double), ("drift12", ctypes.c_double),
         ("nonfinite", ctypes.c_int64),
+        ("eps13", ctypes.c_double), ("sigma13", ctypes.c_double),
+        ("phi_mean", ctypes.c_double), ("vmax", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -73,7 +75,15 @@ class fdm_loading(ctypes.Structure):
     _fields_ = [("strain_rate13", ctypes.c_double), ("tau0", ctypes.c_double),
                 ("mobility", ctypes.c_double), ("mu", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("layer_h", ctypes.c_double),
-                ("cell_l3", ctypes.c_double), ("dt_max", ctypes.c_double)]
+                ("cell_l3", ctypes.c_double), ("dt_max", ctypes.c_double),
+                ("eps13", ctypes.c_double), ("phi_mean", ctypes.c_double)]
+
+
+def loading(strain_rate13: float = 1e-3, tau0: float = 0.01, mobility: float = 1.0, mu: float = 1.0,
+            lam: float = 1.5, layer_h: float = 4.0, cell_l3: float = 512.0, dt_max: float = 0.05,
+            eps13: float = 0.0, phi_mean: float = 0.0) -> fdm_loading:
+    return fdm_loading(float(strain_rate13), float(tau0), float(mobility), float(mu), float(lam), float(layer_h),
+                       float(cell_l3), float(dt_max), float(eps13), float(phi_mean))
 
 
 class FdmError(RuntimeError):

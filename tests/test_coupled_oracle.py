@@ -1,0 +1,83 @@
+"""Pins of the coupled-run oracle (oracle/coupled.py), CPU only."""
+import numpy as np
+import pytest
+
+import oracle as T
+from oracle import coupled as CP
+from oracle import static as S
+from paper_1911_03225_amd import workloads as W
+
+KW = dict(dx=1.0, limiter="minmod", cfl=0.4, time_order=2, mu=1.0, lam=1.5, layer_h=3.0, cell_l3=24.0,
+          mobility=1.0, strain_rate13=2e-3, dt_max=0.25)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    T.build(force=False)
+
+
+def _rings(nx=48, ny=40, seed=2):
+    phi, a11, a12 = W.plateau_rings(nx, ny, seed=seed, count=3, rmin=6.0, rmax=12.0)
+    return phi, a11.astype(np.float64), a12.astype(np.float64)
+
+
+def test_below_threshold_is_elastic_loading():
+    phi, a11, a12 = _rings()
+    b11, b12, hist = CP.coupled_run(a11, a12, 12, 4, tau0=1e9, eps13=0.001, phi_mean=0.03, **KW)
+    assert np.array_equal(b11, a11) and np.array_equal(b12, a12)
+    dt = CP.round_down_float(KW["dt_max"])
+    for r in hist:
+        assert r["vmax"] == 0.0 and r["dt"] == dt and r["phi_mean"] == 0.03
+        t = r["step"] * dt
+        assert r["t"] == pytest.approx(t, rel=1e-15)
+        sig = 2 * (0.001 + KW["strain_rate13"] * t) - 0.03 * 3 / 24
+        assert r["sigma13"] == pytest.approx(sig, rel=1e-13, abs=1e-15)
+
+
+def test_densities_conserved_and_slip_relaxes_the_load():
+    phi, a11, a12 = _rings()
+    s0 = T.stats(a11, a12)
+    b11, b12, hist = CP.coupled_run(a11, a12, 60, 20, tau0=0.005, eps13=0.02, phi_mean=float(phi.mean()), **KW)
+    s1 = T.stats(b11, b12)
+    assert abs(s1["sum11"] - s0["sum11"]) < 1e-11 and abs(s1["sum12"] - s0["sum12"]) < 1e-11
+    assert not np.array_equal(b12, a12)                # fronts moved
+    last = hist[-1]
+    elastic = 2 * last["eps13"] - phi.mean() * 3 / 24
+    assert last["phi_mean"] > phi.mean() and last["sigma13"] < elastic
+
+
+def test_mean_slip_matches_the_phi_form_of_the_step():
+    # Integrate phi itself with the same Hhat fields (phi^{n+1} = phi - dt/2
+    # (Hhat(w^n) + Hhat(w^(1)))): its differences are the densities the
+    # transport produced and its mean is the tracked mean slip.
+    phi, _, _ = _rings(seed=5)
+    # float64 differences of phi: exactly compatible densities (the float32
+    # ones of the workload are not the gradient of any phi to 1e-13)
+    ph = phi.copy()
+    a12 = np.roll(ph, -1, axis=1) - ph
+    a11 = -(np.roll(ph, -1, axis=0) - ph)
+    eps, pm = 0.02, float(phi.mean())
+    ny, nx = a11.shape
+    c11, c12 = a11.copy(), a12.copy()
+    for _ in range(8):
+        tau = S.static_tau13(c11, c12, 1.0, 1.0, 1.0, 1.5, 3, 24, eps, pm)
+        v0 = (-CP.soft_threshold(tau, 0.005)).astype(np.float32).astype(np.float64)
+        vmax = np.max(np.abs(v0))
+        dt = CP.round_down_float(min(0.4 / vmax, KW["dt_max"]) if vmax > 0 else KW["dt_max"])
+        P = T.Problem(nx, ny, limiter="minmod", v0=v0, time_order=2, dt=dt)
+        Pe = T.Problem(nx, ny, limiter="minmod", v0=v0, time_order=1, dt=dt)
+        H1 = T.hhat_field(P, c11, c12)
+        w11, w12 = T.run(Pe, c11, c12, 1)
+        H2 = T.hhat_field(P, w11, w12)
+        ph = ph - 0.5 * dt * (H1 + H2)
+        c11, c12 = T.run(P, c11, c12, 1)
+        pm -= dt * 0.5 * (H1.mean() + H2.mean())
+        eps += KW["strain_rate13"] * dt
+    d12 = np.roll(ph, -1, axis=1) - ph
+    d11 = -(np.roll(ph, -1, axis=0) - ph)
+    assert np.max(np.abs(d12 - c12)) < 1e-13 and np.max(np.abs(d11 - c11)) < 1e-13
+    assert abs(ph.mean() - pm) < 1e-14
+    # and the oracle's run tracks the same numbers
+    b11, b12, hist = CP.coupled_run(a11, a12, 8, 8, tau0=0.005, eps13=0.02, phi_mean=float(phi.mean()), **KW)
+    assert np.array_equal(b11, c11) and np.array_equal(b12, c12)
+    assert hist[-1]["phi_mean"] == pytest.approx(pm, abs=1e-15)

@@ -1,0 +1,124 @@
+"""Coupled run (fdm_run with a loading) against the FP64 oracle of
+oracle/coupled.py: per step the static solve, the threshold velocity law,
+the adaptive step, the transport with v0 frozen and the mean-slip update.
+
+FP64 precision (double state and FFTs) follows the oracle to 1e-10: the
+only differences are FFT and summation rounding (~1e-15), which reach the
+float32 celerity field only across a rounding boundary.  FP32 (single FFTs,
+float32 state) is held to the transport bar, 1e-5 relative L1 per started
+1000 steps, and 1e-6 on the macroscopic quantities."""
+import numpy as np
+import pytest
+
+from gpu_util import to_dev
+from oracle import coupled as CP
+from paper_1911_03225_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+LOAD = dict(strain_rate13=2e-3, tau0=0.005, mobility=1.0, mu=1.0, lam=1.5, layer_h=3.0, cell_l3=24.0,
+            dt_max=0.25, eps13=0.02)
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_03225_amd import fdm as F
+    F.load_library()
+    return F
+
+
+def _gpu(fdm, a11, a12, n_steps, chunk, precision, phi_mean, limiter="minmod", time_order=2, **load):
+    import torch
+    ny, nx = a11.shape
+    dt = np.float64 if precision == "fp64" else np.float32
+    t11, t12 = to_dev(a11, dt), to_dev(a12, dt)
+    ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, limiter=limiter, cfl=0.4, v0=-1.0, time_order=time_order),
+                                 options={"precision": precision})
+    L = fdm.loading(phi_mean=phi_mean, **dict(LOAD, **load))
+    hist = fdm.fdm_run(ctx, t11, t12, n_steps, chunk, loading=L)
+    torch.cuda.synchronize()
+    out = (t11.cpu().numpy().astype(np.float64), t12.cpu().numpy().astype(np.float64))
+    return ctx, [h[0] for h in hist], out, (t11, t12)
+
+
+def _case(seed=2, nx=96, ny=80):
+    phi, a11, a12 = W.plateau_rings(nx, ny, seed=seed, count=4, rmin=8.0, rmax=20.0)
+    return phi, a11, a12
+
+
+@pytest.mark.parametrize("time_order", [2, 1])
+def test_coupled_fp64_matches_oracle(fdm, time_order):
+    phi, a11, a12 = _case()
+    n, chunk = 60, 20
+    ctx, hist, (g11, g12), _ = _gpu(fdm, a11, a12, n, chunk, "fp64", float(phi.mean()), time_order=time_order)
+    o11, o12, ohist = CP.coupled_run(a11, a12, n, chunk, cfl=0.4, time_order=time_order, dx=1.0,
+                                     phi_mean=float(phi.mean()), **LOAD)
+    fdm.fdm_destroy(ctx)
+    assert len(hist) == len(ohist) == 3
+    for g, o in zip(hist, ohist):
+        assert g["step"] == o["step"]
+        assert g["dt"] == o["dt"] and g["vmax"] == pytest.approx(o["vmax"], rel=1e-6)
+        for k in ("t", "eps13", "phi_mean", "sigma13"):
+            assert g[k] == pytest.approx(o[k], rel=1e-10, abs=1e-13), (k, g[k], o[k])
+    den = np.abs(a11).sum() + np.abs(a12).sum()
+    assert (np.abs(g11 - o11).sum() + np.abs(g12 - o12).sum()) / den < 1e-10
+    assert hist[-1]["vmax"] > 0 and hist[-1]["phi_mean"] > float(phi.mean())   # loops moved, slip relaxes
+
+
+def test_coupled_fp32_follows_oracle(fdm):
+    phi, a11, a12 = _case(seed=7)
+    n, chunk = 100, 25
+    ctx, hist, (g11, g12), _ = _gpu(fdm, a11, a12, n, chunk, "fp32", float(phi.mean()))
+    o11, o12, ohist = CP.coupled_run(a11, a12, n, chunk, cfl=0.4, dx=1.0, phi_mean=float(phi.mean()), **LOAD)
+    fdm.fdm_destroy(ctx)
+    worst = {}
+    for g, o in zip(hist, ohist):
+        for k in ("t", "eps13", "phi_mean", "sigma13"):
+            worst[k] = max(worst.get(k, 0.0), abs(g[k] - o[k]) / max(abs(o[k]), 1e-12))
+    den = np.abs(a11).sum() + np.abs(a12).sum()
+    l1 = (np.abs(g11 - o11).sum() + np.abs(g12 - o12).sum()) / den
+    print("fp32 coupled worst relative:", worst, "state rel L1 %.3e" % l1)
+    # measured: phi_mean 2e-8, sigma13 7e-10 relative, state 3.5e-7 relative L1;
+    # the transport bar (1e-5 per started 1000 steps) holds for the state
+    assert all(v < 1e-6 for v in worst.values()), worst
+    assert l1 < 1e-5
+
+
+def test_uncoupled_state_restored_after_a_coupled_run(fdm):
+    import torch
+    phi, a11, a12 = _case(seed=3, nx=64, ny=64)
+    ctx, hist, _, (t11, t12) = _gpu(fdm, a11, a12, 5, 5, "fp32", float(phi.mean()))
+    assert fdm.fdm_transport_dt(ctx) == pytest.approx(0.4)           # the descriptor's CFL step, |v0| = 1
+    before = t12.clone()
+    fdm.fdm_transport_step(ctx, t11, t12, 3)
+    st = fdm.fdm_transport_stats(ctx, t11, t12)[0]
+    assert st["step"] == 8 and st["dt"] == pytest.approx(0.4)
+    assert not torch.equal(before, t12)
+    fdm.fdm_destroy(ctx)
+
+
+def test_coupled_argument_errors(fdm):
+    phi, a11, a12 = _case(seed=3, nx=32, ny=32)
+    t11, t12 = to_dev(a11), to_dev(a12)
+    L = fdm.loading(**LOAD)
+    two = fdm.fdm_transport_init([fdm.desc(32, 32), fdm.desc(32, 32)])
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_run(two, [t11, t11.clone()], [t12, t12.clone()], 2, 1, loading=L)
+    assert e.value.status == fdm.FDM_ERR_INVALID_ARG and "one instance" in fdm.fdm_last_error(two)
+    fdm.fdm_destroy(two)
+    for kw, msg in [(dict(dt=0.1), "CFL-controlled"), (dict(velocity="prescribed", V=(1.0, 0.0)), "LAW"),
+                    (dict(dy=0.5), "dx must equal dy")]:
+        ctx = fdm.fdm_transport_init(fdm.desc(32, 32, **kw))
+        with pytest.raises(fdm.FdmError) as e:
+            fdm.fdm_run(ctx, t11, t12, 2, 1, loading=L)
+        assert e.value.status == fdm.FDM_ERR_INVALID_ARG and msg in fdm.fdm_last_error(ctx)
+        fdm.fdm_destroy(ctx)
+    ctx = fdm.fdm_transport_init(fdm.desc(32, 32))
+    for bad in (dict(tau0=-1.0), dict(dt_max=0.0), dict(layer_h=2.5), dict(cell_l3=2.0)):
+        with pytest.raises(fdm.FdmError) as e:
+            fdm.fdm_run(ctx, t11, t12, 2, 1, loading=fdm.loading(**dict(LOAD, **bad)))
+        assert e.value.status == fdm.FDM_ERR_INVALID_ARG
+    fdm.fdm_destroy(ctx)
