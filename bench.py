@@ -218,6 +218,38 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
             "bitwise_equal": bool(same)}
 
 
+def coupled_leg(fdm, workloads, n_steps, log, n=512):
+    """The coupled workload: a 512^2 layer with 20 seeded loops (plateaus
+    +-0.2, erfc edges sigma 2, radii 20-80), a 4-voxel layer in a 512-voxel
+    cell, mu = 1, nu = 0.3, threshold 0.01, mobility 1, strain rate 1e-3,
+    CFL 0.4 with the step capped at 0.02; n_steps coupled steps (static
+    solve, velocity law, adaptive step, transport, mean slip) in 10 chunks."""
+    import torch
+    phi, a11, a12 = workloads.plateau_rings(n, n, seed=4)
+    dev = torch.device("cuda:0")
+    t11, t12 = torch.from_numpy(a11).to(dev), torch.from_numpy(a12).to(dev)
+    stream = torch.cuda.current_stream()
+    ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter="minmod", cfl=0.4, v0=-1.0), stream=stream)
+    L = fdm.loading(strain_rate13=1e-3, tau0=0.01, mobility=1.0, mu=1.0, lam=1.5, layer_h=4.0, cell_l3=512.0,
+                    dt_max=0.02, eps13=0.0, phi_mean=float(phi.mean()))
+    chunk = max(1, n_steps // 10)
+    fdm.fdm_run(ctx, t11.clone(), t12.clone(), 20, 20, loading=L)    # plans, workspace, warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = fdm.fdm_run(ctx, t11, t12, n_steps, chunk, loading=L)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    fdm.fdm_destroy(ctx)
+    log("bench[c4]: %d coupled steps in %.3f s (%.1f us/step)" % (n_steps, sec, 1e6 * sec / n_steps))
+    return {"grid": [n, n], "steps": n_steps, "seconds": round(sec, 4),
+            "ms_per_step": round(1e3 * sec / n_steps, 4),
+            "cell_updates_per_s": round(n * n * n_steps / sec, 1),
+            "timing": "host wall clock over the call (each step synchronizes twice)",
+            "stress_strain": [[round(r[0]["eps13"], 7), round(r[0]["sigma13"], 8), round(r[0]["phi_mean"], 8),
+                               round(r[0]["vmax"], 6)] for r in hist],
+            "stress_strain_columns": ["eps13", "sigma13", "phi_mean", "vmax"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +266,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64_arith", "fp64"])
     ap.add_argument("--no-c5", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--c5-steps", type=int, default=500)
+    ap.add_argument("--no-c4", action="store_true", help="skip the coupled-run measurement")
+    ap.add_argument("--c4-steps", type=int, default=5000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="N",
                     help="also run one single-stage (Euler) step on an N x N zero state: its copy-back is a "
                          "plain copy kernel reading and writing 4*N*N bytes per array, the byte reference for "
@@ -336,6 +370,10 @@ def main():
     if not args.no_c5:
         c5 = batched_vs_plain(fdm, workloads, args.c5_steps, log, autotune=not args.no_autotune)
 
+    c4 = None
+    if not args.no_c4:
+        c4 = coupled_leg(fdm, workloads, args.c4_steps, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -370,6 +408,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_vs_plain": c5,
+        "coupled": c4,
         "final_stats": {"step": final["step"], "sum_abs": final["sum_abs"], "max_norm": final["max_norm"],
                         "drift11": final["drift11"], "drift12": final["drift12"]},
     }

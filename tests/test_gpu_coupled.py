@@ -122,3 +122,20 @@ def test_coupled_argument_errors(fdm):
             fdm.fdm_run(ctx, t11, t12, 2, 1, loading=fdm.loading(**dict(LOAD, **bad)))
         assert e.value.status == fdm.FDM_ERR_INVALID_ARG
     fdm.fdm_destroy(ctx)
+
+
+def test_coupled_workload_full_size_first_steps(fdm):
+    # the bench's coupled workload (512^2, 20 loops, 4 of 512 voxels) for its
+    # first 20 steps, FP32 against the FP64 oracle
+    phi, a11, a12 = W.plateau_rings(512, 512, seed=4)
+    load = dict(strain_rate13=1e-3, tau0=0.01, mobility=1.0, mu=1.0, lam=1.5, layer_h=4.0, cell_l3=512.0,
+                dt_max=0.02, eps13=0.0)
+    ctx, hist, (g11, g12), _ = _gpu(fdm, a11, a12, 20, 10, "fp32", float(phi.mean()), **load)
+    fdm.fdm_destroy(ctx)
+    o11, o12, ohist = CP.coupled_run(a11, a12, 20, 10, cfl=0.4, dx=1.0, phi_mean=float(phi.mean()), **load)
+    for g, o in zip(hist, ohist):
+        assert g["dt"] == o["dt"]
+        for k in ("eps13", "phi_mean", "sigma13"):
+            assert g[k] == pytest.approx(o[k], rel=1e-6, abs=1e-12), (k, g[k], o[k])
+    den = np.abs(a11).sum() + np.abs(a12).sum()
+    assert (np.abs(g11 - o11).sum() + np.abs(g12 - o12).sum()) / den < 1e-5
