@@ -40,8 +40,8 @@ OPS_PER_NODE_STAGE = 120
 # kernel of known size) and tied to the kernel sources it was measured on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_c2_2048_fp32_traffic.json")
 KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_kernels.hip"]
-STAGE_NAMES = {"fwd": "stage_kernel<float, float, 2, 0, false, 0>",
-               "heun2": "stage_kernel<float, float, 2, 0, false, 2>"}
+STAGE_NAMES = {"fwd": "stage_kernel<float, float, 2, 0, false, 0, false>",
+               "heun2": "stage_kernel<float, float, 2, 0, false, 2, false>"}
 COPY_NAME = "copy_kernel<float>"
 
 
