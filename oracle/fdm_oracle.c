@@ -45,8 +45,10 @@
  *           along x) the weights are 1/2 and the x viscosity term is zero.
  *   Time    time_order = 1: one forward-Euler stage of the semi-discrete
  *           scheme (the dt -> 0 form of the printed single stage);
- *           time_order = 2: two-stage SSP Runge-Kutta (Heun).  The celerity
- *           is frozen over the whole step, as in sec. 3.2.2.
+ *           time_order = 2: two-stage SSP Runge-Kutta (Heun);
+ *           time_order = 3: explicit midpoint (the "midpoint rule" the
+ *           paper names for its second-order step, sec. 3.2.2).  The
+ *           celerity is frozen over the whole step, as in sec. 3.2.2.
  *
  * Hamiltonians:  LAW        H = v0 |p|    (eq. 52 / 56), dH/dp = v0 p/|p|,
  *                                          taken as 0 at p = 0;
@@ -79,7 +81,7 @@ typedef struct {
     double v0;               /* uniform celerity when v0_field is NULL     */
     double V1, V2;           /* prescribed velocity                        */
     const double *v0_field;  /* nx*ny celerity at nodes, or NULL           */
-    int32_t time_order;      /* 1 or 2                                     */
+    int32_t time_order;      /* 1, 2 (Heun) or 3 (explicit midpoint)       */
     int32_t reserved;
     double dt;               /* time step                                  */
 } orc_problem;
@@ -286,6 +288,22 @@ void orc_step(const orc_problem *P, double *a11, double *a12)
             a11[i] = a11[i] + dt * r11[i];
             a12[i] = a12[i] + dt * r12[i];
         }
+    } else if (P->time_order == 3) {
+        /* explicit midpoint: u1 = u + (dt/2) L(u);  u_new = u + dt L(u1). */
+        double *u11 = (double *)malloc(sizeof(double) * n);
+        double *u12 = (double *)malloc(sizeof(double) * n);
+        const double hdt = 0.5 * dt;
+        for (int64_t i = 0; i < n; ++i) {
+            u11[i] = a11[i] + hdt * r11[i];
+            u12[i] = a12[i] + hdt * r12[i];
+        }
+        orc_stage_rate(P, u11, u12, r11, r12);
+        for (int64_t i = 0; i < n; ++i) {
+            a11[i] = a11[i] + dt * r11[i];
+            a12[i] = a12[i] + dt * r12[i];
+        }
+        free(u11);
+        free(u12);
     } else {
         /* Heun: u1 = u + dt L(u);  u_new = u/2 + (u1 + dt L(u1))/2. */
         double *u11 = (double *)malloc(sizeof(double) * n);

@@ -432,7 +432,7 @@ def test_order_of_accuracy(oracle, limiter):
     the compressive limiters stops converging on fine grids: forward Euler is
     anti-diffusive for them, see the overshoot test below.)"""
     L, T, nu = 1.0, 0.25, 0.3
-    cases = [(2, 1.6, 2.3)] + ([(1, 0.75, 1.3)] if limiter == "minmod" else [])
+    cases = [(2, 1.6, 2.3), (3, 1.6, 2.3)] + ([(1, 0.75, 1.3)] if limiter == "minmod" else [])
     for order, lo, hi in cases:
         errs = []
         for n in (32, 64, 128):
@@ -473,3 +473,48 @@ def test_single_stage_overshoots_with_compressive_limiters(oracle, limiter):
         peaks[order] = np.max(np.hypot(b11, b12)) / peak0
     assert peaks[1] > 1.1
     assert 0.9 < peaks[2] < 1.05
+
+
+@pytest.mark.parametrize("limiter", ["mc", "superbee"])
+def test_midpoint_keeps_the_ring_like_heun(oracle, limiter):
+    """The explicit midpoint (time_order 3) is the other second-order reading
+    of the paper's 'midpoint rule': no overshoot either."""
+    n, R, sigma = 128, 30.0, 3.0
+    a11, a12 = W.ring(n, n, R, sigma)
+    peak0 = np.max(np.hypot(a11.astype(np.float64), a12.astype(np.float64)))
+    P = oracle.Problem(n, n, limiter=limiter, v0=-1.0, time_order=3)
+    P.dt = oracle.cfl_dt(P, 0.4)
+    b11, b12 = oracle.run(P, a11, a12, 50)
+    assert 0.9 < np.max(np.hypot(b11, b12)) / peak0 < 1.05
+
+
+def test_midpoint_equals_heun_on_the_linear_scheme(oracle):
+    """For a linear semi-discrete system u' = A u both two-stage methods are
+    u + dt A u + dt^2/2 A^2 u; with H = V.p and no limiter the scheme is
+    linear, so they agree to rounding."""
+    n = 48
+    a11, a12 = densities(_sine_phi(n, 1.0, 0.0), 1.0 / n, 1.0 / n)
+    out = {}
+    for order in (2, 3):
+        P = oracle.Problem(n, n, dx=1.0 / n, dy=1.0 / n, limiter="none", vkind="prescribed", V=(1.0, -0.7),
+                           time_order=order, dt=0.3 / n)
+        out[order] = oracle.run(P, a11, a12, 25)
+    scale = np.max(np.abs(out[2][1]))
+    assert np.max(np.abs(out[2][0] - out[3][0])) < 1e-13 * scale
+    assert np.max(np.abs(out[2][1] - out[3][1])) < 1e-13 * scale
+    # with a limiter it is nonlinear and they differ
+    P2 = oracle.Problem(n, n, dx=1.0 / n, dy=1.0 / n, limiter="mc", vkind="prescribed", V=(1.0, -0.7),
+                        time_order=2, dt=0.3 / n)
+    P3 = oracle.Problem(n, n, dx=1.0 / n, dy=1.0 / n, limiter="mc", vkind="prescribed", V=(1.0, -0.7),
+                        time_order=3, dt=0.3 / n)
+    assert not np.allclose(oracle.run(P2, a11, a12, 25)[1], oracle.run(P3, a11, a12, 25)[1], rtol=0, atol=1e-9)
+
+
+def test_midpoint_conserves(oracle):
+    a11, a12 = W.ring(96, 80, 20.0, 3.0)
+    P = oracle.Problem(96, 80, limiter="superbee", v0=-1.0, time_order=3)
+    P.dt = oracle.cfl_dt(P, 0.4)
+    s0 = oracle.stats(a11, a12)
+    b11, b12 = oracle.run(P, a11, a12, 40)
+    s1 = oracle.stats(b11, b12)
+    assert abs(s1["sum11"] - s0["sum11"]) < 1e-10 and abs(s1["sum12"] - s0["sum12"]) < 1e-10
