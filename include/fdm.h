@@ -88,7 +88,9 @@ typedef struct fdm_transport_desc {
     double theta;            /* FDM_LIMITER_THETA only, in [1, 2]               */
     int32_t time_order;      /* 1: one forward-Euler stage of the semi-discrete
                                 scheme; 2: two-stage SSP Runge-Kutta (Heun),
-                                the default when 0 is given                      */
+                                the default when 0 is given; 3: explicit
+                                midpoint (u + dt L(u + dt/2 L(u)), the
+                                midpoint rule of sec. 3.2.2)                     */
     double cfl;              /* Courant number nu in (0, 1] used when dt == 0   */
     double dt;               /* 0: dt = nu min(dx,dy) / s_max rounded down to a
                                 float; > 0: this step (rounded to the nearest
@@ -225,8 +227,9 @@ fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11,
  *      U^p_13 where tau13 > tau0), stored as float32;
  *   3. dt = the largest float <= min(cfl min(dx,dy) / max|v0|, dt_max)
  *      (dt_max when v0 = 0), cfl from the descriptor;
- *   4. one transport step (Heun or Euler, time_order) with v0 frozen;
- *   5. phi_mean -= dt * mean Hhat (Heun: the mean of the two stages' means),
+ *   4. one transport step (time_order) with v0 frozen;
+ *   5. phi_mean -= dt * mean Hhat (Euler: of the state; Heun: the mean of
+ *      the two stages' means; midpoint: of the half-step state),
  *      eps13 += strain_rate13 * dt.
  * eps13 and phi_mean give the state at the start of the call; the stats
  * records report it after each chunk. */

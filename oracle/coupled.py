@@ -14,9 +14,10 @@ case of sec. 3.2.1:
 3. dt = the largest float not above min(cfl min(dx,dy) / max|v0|, dt_max);
 4. one step of the FP64 transport oracle with v0 frozen over the step;
 5. the mean of phi = U^p_13, which the densities do not carry, follows
-   phi_{n+1} = phi_n - dt Hhat (Euler) or the Heun average of the two stages'
-   Hhat, so its mean moves by -dt times the mean of Hhat; the mean strain
-   moves by strain_rate13 * dt.
+   phi_{n+1} = phi_n - dt Hhat (Euler), the Heun average of the two stages'
+   Hhat, or Hhat of the half-step state (explicit midpoint), so its mean
+   moves by -dt times the mean of that Hhat; the mean strain moves by
+   strain_rate13 * dt.
 """
 from __future__ import annotations
 
@@ -57,10 +58,14 @@ def coupled_run(a11, a12, n_steps: int, chunk: int, *, dx: float = 1.0, limiter:
         dt = round_down_float(min(cfl * dx / vmax, dt_max) if vmax > 0.0 else dt_max)
         P = T.Problem(nx, ny, dx, dx, limiter=limiter, theta=theta, v0=v0, time_order=time_order, dt=dt)
         hmean = float(np.mean(T.hhat_field(P, a11, a12)))
-        if time_order == 2:
+        if time_order == 2:       # Heun: phi - dt/2 (Hhat(u) + Hhat(u + dt L(u)))
             Pe = T.Problem(nx, ny, dx, dx, limiter=limiter, theta=theta, v0=v0, time_order=1, dt=dt)
             w11, w12 = T.run(Pe, a11, a12, 1)
             hmean = 0.5 * (hmean + float(np.mean(T.hhat_field(P, w11, w12))))
+        elif time_order == 3:     # midpoint: phi - dt Hhat(u + dt/2 L(u))
+            Ph = T.Problem(nx, ny, dx, dx, limiter=limiter, theta=theta, v0=v0, time_order=1, dt=0.5 * dt)
+            w11, w12 = T.run(Ph, a11, a12, 1)
+            hmean = float(np.mean(T.hhat_field(P, w11, w12)))
         a11, a12 = T.run(P, a11, a12, 1)
         phi -= dt * hmean
         eps += strain_rate13 * dt

@@ -105,7 +105,7 @@ std::string check_desc(const fdm_transport_desc &d)
     if (d.limiter < FDM_LIMITER_NONE || d.limiter > FDM_LIMITER_SUPERBEE) return "unknown limiter";
     if (d.limiter == FDM_LIMITER_THETA && !(d.theta >= 1.0 && d.theta <= 2.0))
         return "theta must lie in [1, 2]";
-    if (d.time_order != 0 && d.time_order != 1 && d.time_order != 2) return "time_order must be 1 or 2";
+    if (d.time_order < 0 || d.time_order > 3) return "time_order must be 1, 2 or 3";
     if (!(std::isfinite(d.dt) && d.dt >= 0.0)) return "dt must be finite and >= 0";
     if (d.dt == 0.0 && !(d.cfl > 0.0 && d.cfl <= 1.0)) return "cfl must lie in (0, 1]";
     if (d.velocity != FDM_VELOCITY_LAW && d.velocity != FDM_VELOCITY_PRESCRIBED)
@@ -246,6 +246,10 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
         if (c->time_order == 2) {
             modes[0] = fdm::MODE_FWD;
             modes[1] = fdm::MODE_HEUN2;
+            nm = 2;
+        } else if (c->time_order == 3) {
+            modes[0] = fdm::MODE_MID1;
+            modes[1] = fdm::MODE_MID2;
             nm = 2;
         } else {
             modes[0] = (step & 1) ? fdm::MODE_BWD : fdm::MODE_FWD;
@@ -445,7 +449,7 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
     w.phi_mean = phi;
     w.sigma13 = 2.0 * mu * eps - mu * frac * phi;
     std::vector<float> absmax(fdm::kAbsmaxBlocks);
-    const int stages = c->time_order == 2 ? 2 : 1;
+    const int stages = c->time_order == 1 ? 1 : 2;
     int32_t rec = 0;
     for (int32_t step = 0; step < n_steps; ++step) {
         // 1-2. stress of the current state, then the celerity field
@@ -474,10 +478,11 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
         I.cx = (float)I.cxd;
         I.cy = (float)I.cyd;
         I.hsum = w.d_hsum;
-        FDM_HIP(c, fdm::launch_stage(I, fdm::MODE_FWD, c->precision, c->stream));
+        const bool mid = c->time_order == 3;
+        FDM_HIP(c, fdm::launch_stage(I, mid ? fdm::MODE_MID1 : fdm::MODE_FWD, c->precision, c->stream));
         if (stages == 2) {
             I.hsum = w.d_hsum + tiles;
-            FDM_HIP(c, fdm::launch_stage(I, fdm::MODE_HEUN2, c->precision, c->stream));
+            FDM_HIP(c, fdm::launch_stage(I, mid ? fdm::MODE_MID2 : fdm::MODE_HEUN2, c->precision, c->stream));
         } else {
             FDM_HIP(c, fdm::launch_copy(I.a11, I.w11, n, c->precision, c->stream));
             FDM_HIP(c, fdm::launch_copy(I.a12, I.w12, n, c->precision, c->stream));
@@ -486,8 +491,11 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
                                   c->stream));
         FDM_HIP(c, hipStreamSynchronize(c->stream));
         // 5. mean plastic slip and loading
+        // Euler: phi -= dt Hhat(u); Heun: the mean of both stages' Hhat;
+        // midpoint: Hhat of the half-step state only
         double hmean = ordered_sum(w.h_hsum, tiles) / (double)n;
-        if (stages == 2) hmean = 0.5 * (hmean + ordered_sum(w.h_hsum + tiles, tiles) / (double)n);
+        if (c->time_order == 2) hmean = 0.5 * (hmean + ordered_sum(w.h_hsum + tiles, tiles) / (double)n);
+        if (c->time_order == 3) hmean = ordered_sum(w.h_hsum + tiles, tiles) / (double)n;
         phi -= (double)dt * hmean;
         eps += L.strain_rate13 * (double)dt;
         c->steps += 1;

@@ -24,7 +24,10 @@ enum : int { VK_LAW = 0, VK_PRESCRIBED = 1 };
 //   MODE_FWD   : w = a + dt L(a)                 (first stage / Euler step)
 //   MODE_BWD   : a = w + dt L(w)                 (Euler step, other direction)
 //   MODE_HEUN2 : a = a/2 + (w + dt L(w))/2       (second Heun stage, in place)
-enum : int { MODE_FWD = 0, MODE_BWD = 1, MODE_HEUN2 = 2 };
+//   MODE_MID2  : a = a + dt L(w)                 (second midpoint stage, in place)
+//   MODE_MID1  : w = a + (dt/2) L(a)             (first midpoint stage: the
+//                MODE_FWD kernel with the step coefficients halved, exactly)
+enum : int { MODE_FWD = 0, MODE_BWD = 1, MODE_HEUN2 = 2, MODE_MID2 = 3, MODE_MID1 = 4 };
 
 // Precision modes (values of fdm_precision): arithmetic type / state type.
 //   PREC_FP32       float  / float

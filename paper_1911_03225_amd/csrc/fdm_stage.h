@@ -352,7 +352,7 @@ template <typename R, typename S, int LK, int VK, bool FIELD, int MODE, bool HSU
 __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
 {
     constexpr bool kF64 = sizeof(R) == 8;
-    constexpr bool kBase = MODE == MODE_HEUN2;
+    constexpr bool kBase = MODE == MODE_HEUN2 || MODE == MODE_MID2;   // also reads the base state
     const int nx = I.nx, ny = I.ny;
     const void *s12 = MODE == MODE_FWD ? I.a12 : I.w12;
     const void *s11 = MODE == MODE_FWD ? I.a11 : I.w11;
@@ -464,16 +464,18 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
 
         {   // x-edge (j+1/2, k): d(alpha_12)/dt = -(Hhat_{j+1} - Hhat_j)/dx; not on the extra row
             R nv;
-            if constexpr (kF64) nv = wx + I.dtd * (-(hr - hv) / I.dxd);
-            else nv = madd(-cx, hr - hv, wx);
-            if constexpr (kBase) nv = madd(R(0.5), b12, R(0.5) * nv);
+            const R from = MODE == MODE_MID2 ? b12 : wx;   // the state the stage adds to
+            if constexpr (kF64) nv = from + I.dtd * (-(hr - hv) / I.dxd);
+            else nv = madd(-cx, hr - hv, from);
+            if constexpr (MODE == MODE_HEUN2) nv = madd(R(0.5), b12, R(0.5) * nv);
             put(row_ptr<S>(d12, k, nx, it < nrows), off_st, S(nv));
         }
         {   // y-edge (j, k-1/2): d(alpha_11)/dt = (Hhat_k - Hhat_{k-1})/dy; from the second row on
             R nv;
-            if constexpr (kF64) nv = ym1 + I.dtd * ((hv - hprev) / I.dyd);
-            else nv = madd(cy, hv - hprev, ym1);
-            if constexpr (kBase) nv = madd(R(0.5), b11, R(0.5) * nv);
+            const R from = MODE == MODE_MID2 ? b11 : ym1;
+            if constexpr (kF64) nv = from + I.dtd * ((hv - hprev) / I.dyd);
+            else nv = madd(cy, hv - hprev, from);
+            if constexpr (MODE == MODE_HEUN2) nv = madd(R(0.5), b11, R(0.5) * nv);
             put(row_ptr<S>(d11, kprev, nx, it > 0), off_st, S(nv));
         }
         kprev = k;
@@ -522,11 +524,24 @@ __device__ __forceinline__ int64_t xcd_tile(int blocks_per_xcd)
     return logical * kWavesPerBlock + wave;
 }
 
+// The first midpoint stage runs the MODE_FWD kernel with half the step:
+// halving is exact in float and double, so the coefficients are those of
+// dt/2.
+__device__ __forceinline__ void halve_step(InstDev &I)
+{
+    I.cx *= 0.5f;
+    I.cy *= 0.5f;
+    I.cxd *= 0.5;
+    I.cyd *= 0.5;
+    I.dtd *= 0.5;
+}
+
 template <typename R, typename S, int LK, int VK, bool FIELD, int MODE, bool HSUM = false>
-__global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd)
+__global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd, int half)
 {
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
+    if (half) halve_step(I);
     const int t = (int)tile;
     run_tile<R, S, LK, VK, FIELD, MODE, HSUM>(I, t % I.strips, t / I.strips, threadIdx.x & 63);
 }
@@ -537,11 +552,12 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_
 template <typename R, typename S, int MODE>
 __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__restrict__ insts,
                                                                const int32_t *__restrict__ tile_inst,
-                                                               int64_t total_tiles, int blocks_per_xcd)
+                                                               int64_t total_tiles, int blocks_per_xcd, int half)
 {
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
-    const InstDev I = insts[tile_inst[tile]];
+    InstDev I = insts[tile_inst[tile]];
+    if (half) halve_step(I);
     const int local = (int)(tile - I.tile_begin);
     const int strip = local % I.strips, chunk = local / I.strips;
     const int lane = threadIdx.x & 63;
@@ -568,13 +584,18 @@ hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
     const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
-    if (mode == MODE_FWD)
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_FWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd);
+    if (mode == MODE_FWD || mode == MODE_MID1)
+        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_FWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd,
+                           mode == MODE_MID1 ? 1 : 0);
     else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_BWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_BWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd,
+                           0);
+    else if (mode == MODE_MID2)
+        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_MID2, HSUM>), grid, block, 0, s, I, tiles, per_xcd,
+                           0);
     else
         hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_HEUN2, HSUM>), grid, block, 0, s, I, tiles,
-                           per_xcd);
+                           per_xcd, 0);
     return hipGetLastError();
 }
 
@@ -609,12 +630,18 @@ hipError_t launch_batched_r(const InstDev *d_inst, const int32_t *d_tile_inst, i
     const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
-    if (mode == MODE_FWD)
-        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_FWD>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+    if (mode == MODE_FWD || mode == MODE_MID1)
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_FWD>), grid, block, 0, s, d_inst, d_tile_inst,
+                           total_tiles, per_xcd, mode == MODE_MID1 ? 1 : 0);
     else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_BWD>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_BWD>), grid, block, 0, s, d_inst, d_tile_inst,
+                           total_tiles, per_xcd, 0);
+    else if (mode == MODE_MID2)
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_MID2>), grid, block, 0, s, d_inst, d_tile_inst,
+                           total_tiles, per_xcd, 0);
     else
-        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_HEUN2>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_HEUN2>), grid, block, 0, s, d_inst, d_tile_inst,
+                           total_tiles, per_xcd, 0);
     return hipGetLastError();
 }
 

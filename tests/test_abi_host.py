@@ -71,7 +71,8 @@ BAD = [
     (dict(limiter=7), "limiter"),
     (dict(limiter="theta", theta=2.5), "theta"),
     (dict(limiter="theta", theta=0.9), "theta"),
-    (dict(time_order=3), "time_order"),
+    (dict(time_order=4), "time_order"),
+    (dict(time_order=-1), "time_order"),
     (dict(cfl=0.0), "cfl"),
     (dict(cfl=1.5), "cfl"),
     (dict(dt=-1.0), "dt"),

@@ -49,7 +49,7 @@ def _case(seed=2, nx=96, ny=80):
     return phi, a11, a12
 
 
-@pytest.mark.parametrize("time_order", [2, 1])
+@pytest.mark.parametrize("time_order", [2, 1, 3])
 def test_coupled_fp64_matches_oracle(fdm, time_order):
     phi, a11, a12 = _case()
     n, chunk = 60, 20

@@ -530,10 +530,16 @@ def _bitwise_cases():
     a11, a12 = W.ring(61, 67, R=12.0, sigma=3.0)
     cases.append(("euler-prescribed", a11, a12, dict(limiter="superbee", time_order=1, velocity="prescribed",
                                                      V=(0.7, -0.4), cfl=0.5), 31))
+    a11, a12 = W.ring(110, 90, R=20.0, sigma=2.5)
+    cases.append(("midpoint-ring", a11, a12, dict(limiter="superbee", time_order=3, cfl=0.4, v0=-1.0), 70))
+    rng = np.random.default_rng(4)
+    a11, a12 = W.diagonal_bands(88, 72, rng, n_bands=5)
+    v0 = W.fourier_celerity(88, 72, rng, kmax=1)
+    cases.append(("midpoint-field", a11, a12, dict(limiter="minmod", time_order=3, cfl=0.45, v0_field=v0), 60))
     return cases
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(7))
 def test_fp64_state_matches_oracle_bitwise(fdm, oracle, case):
     """FDM_PRECISION_FP64 evaluates the oracle's operations in the oracle's
     order with IEEE arithmetic: the results agree bit for bit."""
@@ -545,3 +551,61 @@ def test_fp64_state_matches_oracle_bitwise(fdm, oracle, case):
     g11, g12 = out[-1][1], out[-1][2]
     d = max(np.max(np.abs(g11 - o11)), np.max(np.abs(g12 - o12)))
     assert d == 0.0, (name, d, rel_l1(g11, g12, o11, o12, a11, a12))
+
+
+# ------------------------------------------------------- explicit midpoint
+
+def test_midpoint_fp32_matches_oracle(fdm, oracle):
+    """time_order 3 (explicit midpoint) on the ring, MC, 600 steps: the
+    float32 path is held to the same loop bound as Heun."""
+    a11, a12 = W.ring(256, 256, R=60.0, sigma=4.0)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 600, every=200, limiter="mc", cfl=0.4, v0=-1.0, time_order=3)
+    for s_, e1, einf in rep:
+        assert e1 <= fp32_loop_bound(s_), (s_, e1, einf)
+
+
+def test_midpoint_smooth_meets_tolerance(fdm, oracle):
+    (a11, a12), dx = W.smooth_sine(128, L=128.0)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 300, every=100, limiter="minmod", cfl=0.4,
+                                velocity="prescribed", V=(1.0, 0.5), time_order=3)
+    for s_, e1, einf in rep:
+        assert e1 <= tolerance(s_), (s_, e1, einf)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_midpoint_tile_rows_schedules_and_graph_bitwise(fdm, precision):
+    from paper_1911_03225_amd import fdm as F
+    rng = np.random.default_rng(6)
+    a11, a12 = W.diagonal_bands(150, 130, rng, n_bands=5)
+    v0 = W.fourier_celerity(150, 130, rng, kmax=1)
+    kw = dict(limiter="superbee", time_order=3, cfl=0.4, v0_field=v0)
+    outs = [gpu_run(a11, a12, 20, options={"tile_rows": r, "precision": precision}, **dict(kw))[1][-1]
+            for r in (1, 5, 12, 64)]
+    for o in outs[1:]:
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+    cases = _mixed_instances()
+    for c in cases:
+        c["limiter"] = "mc"
+    import torch
+    res = {}
+    for sched, use_run in (("plain", False), ("batched", False), ("batched", True)):
+        keep, descs, t11, t12 = [], [], [], []
+        for c in cases:
+            vf = to_dev(c["v0_field"]) if c["v0_field"] is not None else None
+            if vf is not None:
+                keep.append(vf)
+            descs.append(F.desc(c["nx"], c["ny"], limiter="mc", cfl=0.4, v0=c["v0"], v0_field=vf, time_order=3))
+            t11.append(to_dev(c["a11"], state_dtype({"precision": precision})))
+            t12.append(to_dev(c["a12"], state_dtype({"precision": precision})))
+        ctx = F.fdm_transport_init(descs, options={"schedule": sched, "precision": precision}, keep=keep)
+        if use_run:
+            F.fdm_run(ctx, t11, t12, 20, 10)
+        else:
+            F.fdm_transport_step(ctx, t11, t12, 20)
+        torch.cuda.synchronize()
+        res[(sched, use_run)] = [(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(t11, t12)]
+        F.fdm_destroy(ctx)
+    ref = res[("plain", False)]
+    for k, v in res.items():
+        for (a, b), (c_, d) in zip(v, ref):
+            assert np.array_equal(a, c_) and np.array_equal(b, d), k
