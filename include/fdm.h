@@ -221,10 +221,18 @@ fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11,
  *   1. tau13 = fdm_static_solve of the current densities with the current
  *      eps13 and phi_mean (elastic constants, layer_h, cell_l3 below; the
  *      descriptor's dx == dy);
- *   2. celerity v0 = -S(tau13) * mobility at the nodes, S the soft threshold
- *      S(t) = sign(t) max(|t| - tau0, 0) (a threshold law in place of the
- *      paper's lattice-friction energy; v0 < 0 moves fronts so as to raise
- *      U^p_13 where tau13 > tau0), stored as float32;
+ *   2. celerity at the nodes, stored as float32, with m = mobility times
+ *      mobility_field (when given; 0 marks an impenetrable obstacle):
+ *      FDM_LAW_THRESHOLD: v0 = -m S(tau13), S the soft threshold
+ *        S(t) = sign(t) max(|t| - tau0, 0) (a Peierls-type threshold in the
+ *        mobility law, the first lattice-friction approach of sec. 2.3);
+ *      FDM_LAW_WIGGLY: v0 = m (tau_y cos(U^p_13 / beta) - tau13), the wiggly
+ *        energy G = beta sin(U^p_13/beta) tau_y of sec. 3.2.1 (eq. 56 form),
+ *        with U^p_13 = phi at the nodes recovered by the static solve's
+ *        transforms (one more inverse FFT per step).  float32 cannot resolve
+ *        phi / beta for the paper's beta = 1e-8: use FDM_PRECISION_FP64;
+ *      v0 < 0 moves fronts so as to raise U^p_13 where the stress exceeds the
+ *      friction;
  *   3. dt = the largest float <= min(cfl min(dx,dy) / max|v0|, dt_max)
  *      (dt_max when v0 = 0), cfl from the descriptor;
  *   4. one transport step (time_order) with v0 frozen;
@@ -233,14 +241,26 @@ fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11,
  *      eps13 += strain_rate13 * dt.
  * eps13 and phi_mean give the state at the start of the call; the stats
  * records report it after each chunk. */
+typedef enum fdm_law {
+    FDM_LAW_THRESHOLD = 0,
+    FDM_LAW_WIGGLY = 1
+} fdm_law;
+
 typedef struct fdm_loading {
     double strain_rate13;    /* macroscopic shear strain rate                   */
-    double tau0;             /* threshold stress, >= 0                          */
+    double tau0;             /* FDM_LAW_THRESHOLD: threshold stress, >= 0       */
     double mobility;         /* 1 / eta (dimensionless), >= 0                   */
     double mu, lambda, layer_h, cell_l3;   /* as in fdm_static_desc           */
     double dt_max;           /* upper bound on the adaptive step, > 0           */
     double eps13;            /* macroscopic shear strain at the start           */
     double phi_mean;         /* mean of U^p_13 over the layer nodes at start    */
+    int32_t law;             /* fdm_law                                         */
+    int32_t reserved;        /* must be 0                                       */
+    double tau_y;            /* FDM_LAW_WIGGLY: friction amplitude, >= 0        */
+    double beta;             /* FDM_LAW_WIGGLY: energy period, > 0              */
+    const float *mobility_field;  /* optional device array of nx*ny finite
+                                     factors >= 0 on the mobility (0: an
+                                     obstacle the fronts cannot enter), or NULL */
 } fdm_loading;
 
 /* Run n_steps in chunks of `chunk` steps (the last chunk may be shorter).

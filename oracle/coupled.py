@@ -8,9 +8,14 @@ case of sec. 3.2.1:
 
 1. tau13, the layer-averaged shear stress of the current densities and the
    current mean strain and mean slip (``oracle.static``);
-2. the celerity v0 = -S(tau13) * mobility with the soft threshold
-   S(t) = sign(t) max(|t| - tau0, 0), rounded to float32 (the library takes
-   node celerities as float32, like every other input);
+2. the celerity with m = mobility times an optional node factor (0 marks
+   an obstacle, the precipitates of sec. 5), rounded to float32 (the library
+   takes node celerities as float32, like every other input):
+   threshold law  v0 = -m S(tau13), S the soft threshold
+                  S(t) = sign(t) max(|t| - tau0, 0) (sec. 2.3, first approach);
+   wiggly law     v0 = m (tau_y cos(phi / beta) - tau13), the energy
+                  G = beta sin(phi/beta) tau_y of sec. 3.2.1, phi at the nodes
+                  recovered from the densities and their mean;
 3. dt = the largest float not above min(cfl min(dx,dy) / max|v0|, dt_max);
 4. one step of the FP64 transport oracle with v0 frozen over the step;
 5. the mean of phi = U^p_13, which the densities do not carry, follows
@@ -41,7 +46,8 @@ def soft_threshold(t, t0: float):
 def coupled_run(a11, a12, n_steps: int, chunk: int, *, dx: float = 1.0, limiter: str = "minmod",
                 theta=None, cfl: float = 0.4, time_order: int = 2, mu: float = 1.0, lam: float = 1.5,
                 layer_h: float = 4.0, cell_l3: float = 512.0, tau0: float = 0.01, mobility: float = 1.0,
-                strain_rate13: float = 1e-3, dt_max: float = 0.05, eps13: float = 0.0, phi_mean: float = 0.0):
+                strain_rate13: float = 1e-3, dt_max: float = 0.05, eps13: float = 0.0, phi_mean: float = 0.0,
+                law: str = "threshold", tau_y: float = 0.0, beta: float = 1.0, mobility_field=None):
     """Returns (alpha11, alpha12, history); history holds one dict per chunk
     (after its last step): t, dt, step, eps13, sigma13, phi_mean, vmax and
     the density sums."""
@@ -53,7 +59,13 @@ def coupled_run(a11, a12, n_steps: int, chunk: int, *, dx: float = 1.0, limiter:
     history = []
     for step in range(n_steps):
         tau = S.static_tau13(a11, a12, dx, dx, mu, lam, h, n3, eps, phi)
-        v0 = (-soft_threshold(tau, tau0) * mobility).astype(np.float32).astype(np.float64)
+        m = mobility if mobility_field is None else mobility * np.asarray(mobility_field, np.float32).astype(np.float64)
+        if law == "wiggly":
+            nodes = S.phi_from_alpha(a11, a12, dx, dx, phi)
+            v0 = m * (tau_y * np.cos(nodes / beta) - tau)
+        else:
+            v0 = -(m * soft_threshold(tau, tau0))
+        v0 = v0.astype(np.float32).astype(np.float64)
         vmax = float(np.max(np.abs(v0)))
         dt = round_down_float(min(cfl * dx / vmax, dt_max) if vmax > 0.0 else dt_max)
         P = T.Problem(nx, ny, dx, dx, limiter=limiter, theta=theta, v0=v0, time_order=time_order, dt=dt)

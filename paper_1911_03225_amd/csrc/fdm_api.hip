@@ -56,6 +56,7 @@ struct fdm_ctx {
         fdm::StaticPlan *plan = nullptr;
         fdm::StaticParams q{};
         void *tau = nullptr;                // nx*ny, state type
+        void *phi = nullptr;                // nx*ny, state type (wiggly law)
         float *v0 = nullptr;                // nx*ny celerity of the run
         double *d_hsum = nullptr;           // per-tile sums of Hhat, two stages
         double *h_hsum = nullptr;           // pinned copy
@@ -200,6 +201,7 @@ void release(fdm_ctx *c)
     if (c->capture) (void)hipStreamDestroy(c->capture);
     fdm::static_plan_destroy(c->cw.plan);
     if (c->cw.tau) (void)hipFree(c->cw.tau);
+    if (c->cw.phi) (void)hipFree(c->cw.phi);
     if (c->cw.v0) (void)hipFree(c->cw.v0);
     if (c->cw.d_hsum) (void)hipFree(c->cw.d_hsum);
     if (c->cw.h_hsum) (void)hipHostFree(c->cw.h_hsum);
@@ -403,6 +405,11 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
           L.mobility >= 0.0))
         return fail(c, FDM_ERR_INVALID_ARG, "strain_rate13 must be finite, tau0 and mobility finite and >= 0");
     if (!finite_pos(L.dt_max)) return fail(c, FDM_ERR_INVALID_ARG, "dt_max must be finite and > 0");
+    if (L.law != FDM_LAW_THRESHOLD && L.law != FDM_LAW_WIGGLY) return fail(c, FDM_ERR_INVALID_ARG, "unknown law");
+    if (L.reserved != 0) return fail(c, FDM_ERR_INVALID_ARG, "loading.reserved must be 0");
+    const bool wiggly = L.law == FDM_LAW_WIGGLY;
+    if (wiggly && !(std::isfinite(L.tau_y) && L.tau_y >= 0.0 && finite_pos(L.beta)))
+        return fail(c, FDM_ERR_INVALID_ARG, "the wiggly law needs tau_y finite and >= 0, beta finite and > 0");
     fdm_static_desc sd{d.nx, d.ny, d.dx, d.dy, L.mu, L.lambda, L.layer_h, L.cell_l3, L.eps13, L.phi_mean,
                        c->precision, 0};
     fdm::StaticParams q;
@@ -429,6 +436,8 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
         w.q = q;
     }
     if (!w.tau) FDM_HIP(c, hipMalloc(&w.tau, (f64 ? sizeof(double) : sizeof(float)) * n));
+    if (wiggly && !w.phi) FDM_HIP(c, hipMalloc(&w.phi, (f64 ? sizeof(double) : sizeof(float)) * n));
+    const fdm::LawParams law{wiggly, L.tau0, L.mobility, L.tau_y, L.beta, L.mobility_field};
     if (!w.v0) FDM_HIP(c, hipMalloc((void **)&w.v0, sizeof(float) * n));
     InstDev I = c->inst[0];
     const int64_t tiles = (int64_t)I.strips * I.chunks;
@@ -454,9 +463,11 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
     for (int32_t step = 0; step < n_steps; ++step) {
         // 1-2. stress of the current state, then the celerity field
         const double sbar = 2.0 * mu * eps - mu * frac * phi;
-        fdm::StaticStatus ss = fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, sbar, c->stream, err);
+        fdm::StaticStatus ss =
+            wiggly ? fdm::static_plan_run_phi(w.plan, a11[0], a12[0], w.tau, w.phi, sbar, phi, c->stream, err)
+                   : fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, sbar, c->stream, err);
         if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
-        ss = fdm::velocity_law(w.tau, f64, w.v0, n, L.tau0, L.mobility, c->stream, err);
+        ss = fdm::velocity_law(w.tau, w.phi, f64, w.v0, n, law, c->stream, err);
         if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
         // 3. adaptive step
         FDM_HIP(c, fdm::launch_absmax(w.v0, n, c->d_absmax, c->stream));

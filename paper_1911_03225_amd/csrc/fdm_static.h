@@ -29,8 +29,21 @@ void static_plan_destroy(StaticPlan *p);
 StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, double sigma_bar,
                              hipStream_t s, std::string &err);
 
-// v0 = -S_tau0(tau13) * mobility (soft threshold), written as float32.
-StaticStatus velocity_law(const void *tau13, bool f64, float *v0, int64_t n, double tau0, double mobility,
+// As static_plan_run, and also phi (= U^p_13) at the nodes with the given
+// mean, from the same forward transforms.
+StaticStatus static_plan_run_phi(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
+                                 double sigma_bar, double phi_mean, hipStream_t s, std::string &err);
+
+// Celerity at the nodes, written as float32, m = mobility * mfield[i] (mfield
+// may be null):
+//   wiggly = false: v0 = -m S_tau0(tau13), S the soft threshold;
+//   wiggly = true:  v0 = m (tau_y cos(phi / beta) - tau13).
+struct LawParams {
+    bool wiggly;
+    double tau0, mobility, tau_y, beta;
+    const float *mfield;
+};
+StaticStatus velocity_law(const void *tau13, const void *phi, bool f64, float *v0, int64_t n, const LawParams &law,
                           hipStream_t s, std::string &err);
 
 }  // namespace fdm

@@ -101,17 +101,57 @@ __global__ __launch_bounds__(256) void pack_kernel(T *dst, const T *a11, const T
     }
 }
 
-// v0 = -S_tau0(tau13) * mobility, S the soft threshold; float32 field.
-template <typename T>
-__global__ __launch_bounds__(256) void velocity_law_kernel(const T *tau, float *v0, int64_t n, T tau0, T mobility)
+// Celerity field (float32), m = mobility * mfield[i]:
+//   threshold: v0 = -m S_tau0(tau13), S the soft threshold;
+//   wiggly:    v0 = m (tau_y cos(phi / beta) - tau13).
+template <typename T, bool WIGGLY>
+__global__ __launch_bounds__(256) void velocity_law_kernel(const T *tau, const T *phi, const float *mfield, float *v0,
+                                                            int64_t n, T tau0, T mobility, T tau_y, T beta)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const T t = tau[i];
-        const T a = fabs(t) - tau0;
-        const T s = a > T(0) ? copysign(a, t) : T(0);
-        v0[i] = (float)(-s * mobility);
+        const T m = mfield ? mobility * T(mfield[i]) : mobility;
+        T v;
+        if constexpr (WIGGLY) {
+            v = m * (tau_y * cos(phi[i] / beta) - t);
+        } else {
+            const T a = fabs(t) - tau0;
+            const T s = a > T(0) ? copysign(a, t) : T(0);
+            v = -(m * s);
+        }
+        v0[i] = (float)v;
     }
+}
+
+// phi^ / N at every mode (phi_mean at the mean), for a complex-to-real
+// transform; spec holds alpha11^ then alpha12^.
+template <typename T>
+__global__ __launch_bounds__(256) void phi_kernel(const T *spec, T *out, const T *d1, const T *d2, int nxh, int ny,
+                                                   T inv_n, T phi_mean)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nmodes = (int64_t)nxh * ny;
+    if (idx >= nmodes) return;
+    const int m1 = (int)(idx % nxh), m2 = (int)(idx / nxh);
+    T re, im;
+    if (idx == 0) {
+        re = phi_mean;
+        im = T(0);
+    } else {
+        const T a11r = spec[2 * idx], a11i = spec[2 * idx + 1];
+        const T a12r = spec[2 * (nmodes + idx)], a12i = spec[2 * (nmodes + idx) + 1];
+        const T d1r = d1[2 * m1], d1i = d1[2 * m1 + 1];
+        const T d2r = d2[2 * m2], d2i = d2[2 * m2 + 1];
+        const T nr = (d1r * a12r + d1i * a12i) - (d2r * a11r + d2i * a11i);
+        const T ni = (d1r * a12i - d1i * a12r) - (d2r * a11i - d2i * a11r);
+        const T den = (d1r * d1r + d1i * d1i) + (d2r * d2r + d2i * d2i);
+        const T f = inv_n / den;
+        re = f * nr;
+        im = f * ni;
+    }
+    out[2 * idx] = re;
+    out[2 * idx + 1] = im;
 }
 
 std::once_flag g_rocfft_once;
@@ -287,8 +327,26 @@ StaticStatus static_plan_create(const StaticParams &q, hipStream_t s, StaticPlan
     return StaticStatus::Ok;
 }
 
+namespace {
+StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi, double sigma_bar,
+                      double phi_mean, hipStream_t s, std::string &err);
+}
+
 StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, double sigma_bar,
                              hipStream_t s, std::string &err)
+{
+    return run_impl(p, a11, a12, tau13, nullptr, sigma_bar, 0.0, s, err);
+}
+
+StaticStatus static_plan_run_phi(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
+                                 double sigma_bar, double phi_mean, hipStream_t s, std::string &err)
+{
+    return run_impl(p, a11, a12, tau13, phi, sigma_bar, phi_mean, s, err);
+}
+
+namespace {
+StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi, double sigma_bar,
+                      double phi_mean, hipStream_t s, std::string &err)
 {
     const int64_t n = (int64_t)p->nx * p->ny, nm = (int64_t)p->nxh * p->ny;
     ST_FFT(rocfft_execution_info_set_stream(p->info, s));
@@ -304,6 +362,20 @@ StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, vo
     ST_HIP(hipGetLastError());
     void *in[1] = {p->real2}, *outb[1] = {p->spec};
     ST_FFT(rocfft_execute(p->fwd, in, outb, p->info));
+    if (phi) {
+        // phi^ into the (consumed) packed-input buffer, then to the nodes
+        if (p->f64)
+            hipLaunchKernelGGL(phi_kernel<double>, dim3(gb), dim3(256), 0, s, (const double *)p->spec,
+                               (double *)p->real2, (const double *)p->d1, (const double *)p->d2, p->nxh, p->ny,
+                               1.0 / (double)n, phi_mean);
+        else
+            hipLaunchKernelGGL(phi_kernel<float>, dim3(gb), dim3(256), 0, s, (const float *)p->spec,
+                               (float *)p->real2, (const float *)p->d1, (const float *)p->d2, p->nxh, p->ny,
+                               (float)(1.0 / (double)n), (float)phi_mean);
+        ST_HIP(hipGetLastError());
+        void *pin[1] = {p->real2}, *pout[1] = {phi};
+        ST_FFT(rocfft_execute(p->inv, pin, pout, p->info));
+    }
     // the product overwrites alpha11^ in place: each thread reads its own
     // mode of both spectra before writing that mode
     void *prod = p->spec;
@@ -321,17 +393,29 @@ StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, vo
     ST_FFT(rocfft_execute(p->inv, in2, out2, p->info));
     return StaticStatus::Ok;
 }
+}  // namespace
 
-StaticStatus velocity_law(const void *tau13, bool f64, float *v0, int64_t n, double tau0, double mobility,
+StaticStatus velocity_law(const void *tau13, const void *phi, bool f64, float *v0, int64_t n, const LawParams &L,
                           hipStream_t s, std::string &err)
 {
     const unsigned b = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-    if (f64)
-        hipLaunchKernelGGL(velocity_law_kernel<double>, dim3(b), dim3(256), 0, s, (const double *)tau13, v0, n, tau0,
-                           mobility);
-    else
-        hipLaunchKernelGGL(velocity_law_kernel<float>, dim3(b), dim3(256), 0, s, (const float *)tau13, v0, n,
-                           (float)tau0, (float)mobility);
+    if (f64) {
+        if (L.wiggly)
+            hipLaunchKernelGGL((velocity_law_kernel<double, true>), dim3(b), dim3(256), 0, s, (const double *)tau13,
+                               (const double *)phi, L.mfield, v0, n, L.tau0, L.mobility, L.tau_y, L.beta);
+        else
+            hipLaunchKernelGGL((velocity_law_kernel<double, false>), dim3(b), dim3(256), 0, s, (const double *)tau13,
+                               (const double *)phi, L.mfield, v0, n, L.tau0, L.mobility, L.tau_y, L.beta);
+    } else {
+        if (L.wiggly)
+            hipLaunchKernelGGL((velocity_law_kernel<float, true>), dim3(b), dim3(256), 0, s, (const float *)tau13,
+                               (const float *)phi, L.mfield, v0, n, (float)L.tau0, (float)L.mobility,
+                               (float)L.tau_y, (float)L.beta);
+        else
+            hipLaunchKernelGGL((velocity_law_kernel<float, false>), dim3(b), dim3(256), 0, s, (const float *)tau13,
+                               (const float *)phi, L.mfield, v0, n, (float)L.tau0, (float)L.mobility,
+                               (float)L.tau_y, (float)L.beta);
+    }
     ST_HIP(hipGetLastError());
     return StaticStatus::Ok;
 }

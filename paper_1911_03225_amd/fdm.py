@@ -76,14 +76,26 @@ class fdm_loading(ctypes.Structure):
                 ("mobility", ctypes.c_double), ("mu", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("layer_h", ctypes.c_double),
                 ("cell_l3", ctypes.c_double), ("dt_max", ctypes.c_double),
-                ("eps13", ctypes.c_double), ("phi_mean", ctypes.c_double)]
+                ("eps13", ctypes.c_double), ("phi_mean", ctypes.c_double),
+                ("law", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tau_y", ctypes.c_double), ("beta", ctypes.c_double),
+                ("mobility_field", ctypes.c_void_p)]
+
+
+LAWS = {"threshold": 0, "wiggly": 1}
 
 
 def loading(strain_rate13: float = 1e-3, tau0: float = 0.01, mobility: float = 1.0, mu: float = 1.0,
             lam: float = 1.5, layer_h: float = 4.0, cell_l3: float = 512.0, dt_max: float = 0.05,
-            eps13: float = 0.0, phi_mean: float = 0.0) -> fdm_loading:
+            eps13: float = 0.0, phi_mean: float = 0.0, law="threshold", tau_y: float = 0.0, beta: float = 1.0,
+            mobility_field=None) -> fdm_loading:
+    """mobility_field: optional float32 CUDA tensor (ny, nx) of factors on the mobility (keep it alive)."""
+    mf = None
+    if mobility_field is not None:
+        mf = _ptr(mobility_field, None, "mobility_field")
     return fdm_loading(float(strain_rate13), float(tau0), float(mobility), float(mu), float(lam), float(layer_h),
-                       float(cell_l3), float(dt_max), float(eps13), float(phi_mean))
+                       float(cell_l3), float(dt_max), float(eps13), float(phi_mean),
+                       LAWS[law] if isinstance(law, str) else int(law), 0, float(tau_y), float(beta), mf)
 
 
 class FdmError(RuntimeError):

@@ -49,7 +49,7 @@ def test_struct_sizes_match_c_layout(fdm):
     # int32 + pad before each double, pointer-aligned field: the C layout
     assert ctypes.sizeof(fdm.fdm_transport_desc) == 104
     assert ctypes.sizeof(fdm.fdm_stats) == 112
-    assert ctypes.sizeof(fdm.fdm_loading) == 80
+    assert ctypes.sizeof(fdm.fdm_loading) == 112
     assert ctypes.sizeof(fdm.fdm_options) == 16
     assert ctypes.sizeof(fdm.fdm_tune_trial) == 16
     assert ctypes.sizeof(fdm.fdm_static_desc) == 80

@@ -81,3 +81,37 @@ def test_mean_slip_matches_the_phi_form_of_the_step():
     b11, b12, hist = CP.coupled_run(a11, a12, 8, 8, tau0=0.005, eps13=0.02, phi_mean=float(phi.mean()), **KW)
     assert np.array_equal(b11, c11) and np.array_equal(b12, c12)
     assert hist[-1]["phi_mean"] == pytest.approx(pm, abs=1e-15)
+
+
+def test_wiggly_without_friction_is_the_zero_threshold_law():
+    phi, a11, a12 = _rings()
+    kw = dict(KW, eps13=0.02, phi_mean=float(phi.mean()))
+    b = CP.coupled_run(a11, a12, 10, 10, law="wiggly", tau_y=0.0, beta=1e-3, tau0=0.0, **kw)
+    c = CP.coupled_run(a11, a12, 10, 10, law="threshold", tau0=0.0, **kw)
+    assert np.array_equal(b[0], c[0]) and np.array_equal(b[1], c[1])
+    assert b[2][-1]["phi_mean"] == c[2][-1]["phi_mean"]
+
+
+def test_wiggly_friction_slows_the_slip():
+    phi, a11, a12 = _rings()
+    kw = dict(KW, eps13=0.02, phi_mean=float(phi.mean()))
+    free = CP.coupled_run(a11, a12, 40, 40, law="wiggly", tau_y=0.0, beta=1e-3, **kw)[2][-1]["phi_mean"]
+    held = CP.coupled_run(a11, a12, 40, 40, law="wiggly", tau_y=0.03, beta=1e-3, **kw)[2][-1]["phi_mean"]
+    assert phi.mean() < held < free
+
+
+def test_obstacles_do_not_move():
+    phi, a11, a12 = _rings(seed=9)
+    ny, nx = a11.shape
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    field = np.ones((ny, nx), np.float32)
+    inside = (X - 20) ** 2 + (Y - 18) ** 2 < 8 ** 2
+    field[inside] = 0.0
+    b11, b12, _ = CP.coupled_run(a11, a12, 30, 30, tau0=0.002, eps13=0.03, phi_mean=float(phi.mean()),
+                                 mobility_field=field, **{k: v for k, v in KW.items()})
+    # an x-edge (j+1/2, k) joins nodes (j,k), (j+1,k); a y-edge (j, k+1/2) nodes (j,k), (j,k+1)
+    ex = inside & np.roll(inside, -1, axis=1)
+    ey = inside & np.roll(inside, -1, axis=0)
+    assert ex.sum() > 100
+    assert np.array_equal(b12[ex], a12[ex]) and np.array_equal(b11[ey], a11[ey])
+    assert not np.array_equal(b12, a12)
