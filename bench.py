@@ -350,7 +350,12 @@ def main():
                 "kernel_avg_us": round(1e6 * kernel_s, 2), "ops_per_launch": ops_per_launch,
                 "hbm_bytes_per_launch": BYTES_PER_CELL_STEP // 2 * cells,
                 "unfused_min_bytes_per_launch": 20 * cells,
-                "hbm_achieved_gbs": round(BYTES_PER_CELL_STEP / 2 * cells / kernel_s / 1e9, 1)}
+                "hbm_achieved_gbs": round(BYTES_PER_CELL_STEP / 2 * cells / kernel_s / 1e9, 1),
+                # measured L2-to-fabric bytes (counter passes) over this run's launch time;
+                # at 2048^2 the working set sits in the 256 MB MALL, which serves much of it
+                "fabric_achieved_gbs": round(tr["bytes_per_launch"] / kernel_s / 1e9, 1) if tr else None,
+                "fabric_frac_of_hbm_peak": round(tr["bytes_per_launch"] / kernel_s / 1e9 / HBM_PEAK_GBS, 4)
+                if tr else None}
     final = hist[-1][0]
     fdm.fdm_destroy(ctx)
 

@@ -272,8 +272,10 @@ typedef struct fdm_loading {
  * loading != NULL: the coupled run above, for a context of one instance
  * with the LAW velocity and a CFL-controlled step (dt = 0 in its
  * descriptor) and dx == dy; the descriptor's v0 / v0_field are not used
- * during the run (they are again after it).  Each step synchronizes twice
- * (for max |v0| and for the sums of Hhat); the first call allocates the
+ * during the run (they are again after it).  The step size, mean slip and
+ * mean stress are computed on the device, so steps are enqueued without
+ * waiting; the stream is synchronized once per chunk (to read those scalars
+ * back, and for the stats record).  The first call allocates the
  * coupled workspace (FFT plans, a stress and a celerity field, per-tile
  * sums), kept until fdm_destroy. */
 fdm_status fdm_run(fdm_ctx *ctx, const fdm_loading *loading, void *const *alpha11,

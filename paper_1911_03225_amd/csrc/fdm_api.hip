@@ -59,8 +59,9 @@ struct fdm_ctx {
         void *phi = nullptr;                // nx*ny, state type (wiggly law)
         float *v0 = nullptr;                // nx*ny celerity of the run
         double *d_hsum = nullptr;           // per-tile sums of Hhat, two stages
-        double *h_hsum = nullptr;           // pinned copy
         int64_t cap = 0;                    // tiles per stage the sums hold
+        fdm::CoupledDev *d_cd = nullptr;    // step scalars on the device
+        fdm::CoupledDev *h_cd = nullptr;    // pinned mirror
         double eps13 = 0.0, sigma13 = 0.0, phi_mean = 0.0, vmax = 0.0;
     } cw;
     size_t elem = sizeof(float);            // bytes per state value
@@ -204,7 +205,8 @@ void release(fdm_ctx *c)
     if (c->cw.phi) (void)hipFree(c->cw.phi);
     if (c->cw.v0) (void)hipFree(c->cw.v0);
     if (c->cw.d_hsum) (void)hipFree(c->cw.d_hsum);
-    if (c->cw.h_hsum) (void)hipHostFree(c->cw.h_hsum);
+    if (c->cw.d_cd) (void)hipFree(c->cw.d_cd);
+    if (c->cw.h_cd) (void)hipHostFree(c->cw.h_cd);
     delete c;
 }
 
@@ -376,18 +378,6 @@ fdm_status compute_stats(fdm_ctx *c, void *const *a11, void *const *a12, fdm_sta
     return FDM_OK;
 }
 
-// Kahan-Babuska (Neumaier) sum of n doubles in index order.
-double ordered_sum(const double *v, int64_t n)
-{
-    double s = 0.0, comp = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        const double t = s + v[i];
-        comp += std::fabs(s) >= std::fabs(v[i]) ? (s - t) + v[i] : (v[i] - t) + s;
-        s = t;
-    }
-    return s + comp;
-}
-
 fdm_status static_fail(fdm_ctx *c, fdm::StaticStatus st, const std::string &err)
 {
     return fail(c, st == fdm::StaticStatus::OutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE, err);
@@ -443,53 +433,48 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
     const int64_t tiles = (int64_t)I.strips * I.chunks;
     if (tiles > w.cap) {
         if (w.d_hsum) FDM_HIP(c, hipFree(w.d_hsum));
-        if (w.h_hsum) FDM_HIP(c, hipHostFree(w.h_hsum));
         w.d_hsum = nullptr;
-        w.h_hsum = nullptr;
         w.cap = 0;
         FDM_HIP(c, hipMalloc((void **)&w.d_hsum, sizeof(double) * 2 * tiles));
-        FDM_HIP(c, hipHostMalloc((void **)&w.h_hsum, sizeof(double) * 2 * tiles, hipHostMallocDefault));
         w.cap = tiles;
     }
+    if (!w.d_cd) FDM_HIP(c, hipMalloc((void **)&w.d_cd, sizeof(fdm::CoupledDev)));
+    if (!w.h_cd) FDM_HIP(c, hipHostMalloc((void **)&w.h_cd, sizeof(fdm::CoupledDev), hipHostMallocDefault));
 
+    // The step scalars live on the device: each step enqueues its kernels
+    // without waiting (the step size, mean slip and mean stress are computed
+    // by one-block kernels); the host reads them back once per chunk.
     const double h = std::min(d.dx, d.dy), mu = L.mu, frac = (double)q.h / (double)q.n3;
-    double eps = L.eps13, phi = L.phi_mean;
-    w.eps13 = eps;
-    w.phi_mean = phi;
-    w.sigma13 = 2.0 * mu * eps - mu * frac * phi;
-    std::vector<float> absmax(fdm::kAbsmaxBlocks);
+    FDM_HIP(c, hipStreamSynchronize(c->stream));   // the pinned mirror may feed an earlier copy
+    std::memset(w.h_cd, 0, sizeof(fdm::CoupledDev));
+    w.h_cd->eps13 = L.eps13;
+    w.h_cd->phi_mean = L.phi_mean;
+    w.h_cd->t = c->t_acc[0];
+    w.h_cd->sigma_bar = 2.0 * mu * L.eps13 - mu * frac * L.phi_mean;
+    FDM_HIP(c, hipMemcpyAsync(w.d_cd, w.h_cd, sizeof(fdm::CoupledDev), hipMemcpyHostToDevice, c->stream));
+    w.eps13 = L.eps13;
+    w.phi_mean = L.phi_mean;
+    w.sigma13 = w.h_cd->sigma_bar;
+
+    I.v0f = w.v0;
+    I.coef = &w.d_cd->coef;
     const int stages = c->time_order == 1 ? 1 : 2;
+    const bool mid = c->time_order == 3;
     int32_t rec = 0;
     for (int32_t step = 0; step < n_steps; ++step) {
         // 1-2. stress of the current state, then the celerity field
-        const double sbar = 2.0 * mu * eps - mu * frac * phi;
         fdm::StaticStatus ss =
-            wiggly ? fdm::static_plan_run_phi(w.plan, a11[0], a12[0], w.tau, w.phi, sbar, phi, c->stream, err)
-                   : fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, sbar, c->stream, err);
+            wiggly ? fdm::static_plan_run_phi(w.plan, a11[0], a12[0], w.tau, w.phi, &w.d_cd->sigma_bar,
+                                              &w.d_cd->phi_mean, c->stream, err)
+                   : fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, &w.d_cd->sigma_bar, c->stream, err);
         if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
         ss = fdm::velocity_law(w.tau, w.phi, f64, w.v0, n, law, c->stream, err);
         if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
-        // 3. adaptive step
+        // 3. adaptive step, on the device
         FDM_HIP(c, fdm::launch_absmax(w.v0, n, c->d_absmax, c->stream));
-        FDM_HIP(c, hipMemcpyAsync(absmax.data(), c->d_absmax, sizeof(float) * fdm::kAbsmaxBlocks,
-                                  hipMemcpyDeviceToHost, c->stream));
-        FDM_HIP(c, hipStreamSynchronize(c->stream));
-        float vmax = 0.0f;
-        for (float v : absmax) {
-            if (std::isnan(v)) return fail(c, FDM_ERR_NONFINITE, "non-finite celerity in the coupled run");
-            vmax = std::max(vmax, v);
-        }
-        const double bound = vmax > 0.0f ? std::min(d.cfl * h / (double)vmax, L.dt_max) : L.dt_max;
-        const float dt = round_down_float(bound);
+        FDM_HIP(c, fdm::launch_coupled_dt(c->d_absmax, w.d_cd, d.cfl * h, L.dt_max, d.dx, d.dy, c->stream));
         // 4. one transport step with v0 frozen, per-tile sums of Hhat
-        I.v0f = w.v0;
-        I.dtd = (double)dt;
-        I.cxd = (double)dt / d.dx;
-        I.cyd = (double)dt / d.dy;
-        I.cx = (float)I.cxd;
-        I.cy = (float)I.cyd;
         I.hsum = w.d_hsum;
-        const bool mid = c->time_order == 3;
         FDM_HIP(c, fdm::launch_stage(I, mid ? fdm::MODE_MID1 : fdm::MODE_FWD, c->precision, c->stream));
         if (stages == 2) {
             I.hsum = w.d_hsum + tiles;
@@ -498,25 +483,22 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
             FDM_HIP(c, fdm::launch_copy(I.a11, I.w11, n, c->precision, c->stream));
             FDM_HIP(c, fdm::launch_copy(I.a12, I.w12, n, c->precision, c->stream));
         }
-        FDM_HIP(c, hipMemcpyAsync(w.h_hsum, w.d_hsum, sizeof(double) * stages * tiles, hipMemcpyDeviceToHost,
-                                  c->stream));
-        FDM_HIP(c, hipStreamSynchronize(c->stream));
-        // 5. mean plastic slip and loading
-        // Euler: phi -= dt Hhat(u); Heun: the mean of both stages' Hhat;
-        // midpoint: Hhat of the half-step state only
-        double hmean = ordered_sum(w.h_hsum, tiles) / (double)n;
-        if (c->time_order == 2) hmean = 0.5 * (hmean + ordered_sum(w.h_hsum + tiles, tiles) / (double)n);
-        if (c->time_order == 3) hmean = ordered_sum(w.h_hsum + tiles, tiles) / (double)n;
-        phi -= (double)dt * hmean;
-        eps += L.strain_rate13 * (double)dt;
+        // 5. mean slip and loading
+        FDM_HIP(c, fdm::launch_coupled_slip(w.d_hsum, tiles, c->time_order, w.d_cd, L.strain_rate13, mu, frac,
+                                            (double)n, c->stream));
         c->steps += 1;
-        c->t_acc[0] += (double)dt;
-        c->dt_last[0] = dt;
-        w.eps13 = eps;
-        w.phi_mean = phi;
-        w.sigma13 = 2.0 * mu * eps - mu * frac * phi;
-        w.vmax = vmax;
-        if (history && ((step + 1) % chunk == 0 || step + 1 == n_steps)) {
+        const bool chunk_end = (step + 1) % chunk == 0 || step + 1 == n_steps;
+        if (!chunk_end) continue;
+        FDM_HIP(c, hipMemcpyAsync(w.h_cd, w.d_cd, sizeof(fdm::CoupledDev), hipMemcpyDeviceToHost, c->stream));
+        FDM_HIP(c, hipStreamSynchronize(c->stream));
+        if (w.h_cd->coef.nonfinite) return fail(c, FDM_ERR_NONFINITE, "non-finite celerity in the coupled run");
+        c->t_acc[0] = w.h_cd->t;
+        c->dt_last[0] = w.h_cd->coef.dt;
+        w.eps13 = w.h_cd->eps13;
+        w.phi_mean = w.h_cd->phi_mean;
+        w.sigma13 = w.h_cd->sigma_bar;
+        w.vmax = w.h_cd->coef.vmax;
+        if (history) {
             st = compute_stats(c, a11, a12, history + rec);
             if (st != FDM_OK) return st;
             ++rec;
@@ -708,7 +690,15 @@ fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11, co
     fdm::StaticPlan *plan = nullptr;
     fdm::StaticStatus st = fdm::static_plan_create(q, s, &plan, err);
     if (st == fdm::StaticStatus::Ok) {
-        st = fdm::static_plan_run(plan, alpha11, alpha12, tau13_out, static_mean_stress(*desc, q), s, err);
+        const double sbar[2] = {static_mean_stress(*desc, q), desc->phi_mean};
+        const hipError_t ce = hipMemcpyAsync(fdm::static_plan_scalars(plan), sbar, sizeof(sbar),
+                                             hipMemcpyHostToDevice, s);
+        if (ce != hipSuccess) {
+            st = fdm::StaticStatus::Device;
+            err = std::string("hipMemcpyAsync: ") + hipGetErrorString(ce);
+        } else {
+            st = fdm::static_plan_run(plan, alpha11, alpha12, tau13_out, fdm::static_plan_scalars(plan), s, err);
+        }
         const hipError_t e = hipStreamSynchronize(s);
         if (st == fdm::StaticStatus::Ok && e != hipSuccess) {
             st = fdm::StaticStatus::Device;

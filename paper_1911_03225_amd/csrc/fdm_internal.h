@@ -35,6 +35,21 @@ enum : int { MODE_FWD = 0, MODE_BWD = 1, MODE_HEUN2 = 2, MODE_MID2 = 3, MODE_MID
 //   PREC_FP64       double / double
 enum : int { PREC_FP32 = 0, PREC_FP64_ARITH = 1, PREC_FP64 = 2 };
 
+// Step coefficients computed on the device (coupled runs): the stage kernels
+// read them through InstDev::coef instead of the values in InstDev.
+struct StepCoef {
+    double dtd, cxd, cyd;    // dt, dt/dx, dt/dy
+    float cx, cy;            // the same in float
+    float dt, vmax;          // the float32 step and max |v0| it came from
+    int32_t nonfinite, pad;  // a non-finite celerity was seen
+};
+
+// Scalars of a coupled run, advanced on the device step by step.
+struct CoupledDev {
+    StepCoef coef;
+    double eps13, phi_mean, t, sigma_bar;
+};
+
 // Device view of one transport instance.
 struct InstDev {
     void *a11, *a12;         // state, caller-owned (float, or double in PREC_FP64)
@@ -52,6 +67,7 @@ struct InstDev {
     double cxd, cyd, thetad; // the same coefficients for FP64 arithmetic
     double dtd, dxd, dyd;    // step and spacings (FP64 update in definition form)
     double *hsum;            // per-tile sums of Hhat (coupled runs) or nullptr
+    const StepCoef *coef;    // device step coefficients (coupled runs) or nullptr
 };
 
 // Per-block partial of the diagnostics reduction (compensated sums).
@@ -70,5 +86,13 @@ hipError_t launch_stats(const void *a11, const void *a12, int64_t n, int precisi
 hipError_t launch_copy(void *dst, const void *src, int64_t n, int precision, hipStream_t s);
 
 constexpr int kAbsmaxBlocks = 256;
+
+// Coupled runs: step size from the max |v0| partials (largest float not
+// above min(cfl_h / max|v0|, dt_max)); then, after the stages, the mean slip,
+// mean strain, time and mean stress from the per-tile sums of Hhat.
+hipError_t launch_coupled_dt(const float *absmax_partials, CoupledDev *cd, double cfl_h, double dt_max, double dx,
+                             double dy, hipStream_t s);
+hipError_t launch_coupled_slip(const double *hsum, int64_t tiles, int time_order, CoupledDev *cd, double rate,
+                               double mu, double frac, double n_nodes, hipStream_t s);
 
 }  // namespace fdm

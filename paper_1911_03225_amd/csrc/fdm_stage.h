@@ -162,6 +162,36 @@ __device__ __forceinline__ R limited_slope(R wm, R w0, R wp, R theta)
     }
 }
 
+// float, along the y walk: the backward difference of row k is the forward
+// difference of row k-1, bit for bit (same operands, same operation), so it
+// is carried from the previous row together with its scaled form (2 D for
+// superbee, theta D for the minmod family).  Same results as limited_slope,
+// two instructions fewer.  dm, dms: in, the carried difference and its scaled
+// form; out, this row's.
+template <int LK>
+__device__ __forceinline__ float y_slope_carried(float wm, float w0, float wp, float theta, float &dm, float &dms)
+{
+    if constexpr (LK == LK_NONE) {
+        return 0.0f;
+    } else {
+        const float dp = wp - w0;
+        float s, dps;
+        if constexpr (LK == LK_SUPERBEE) {
+            dps = 2.0f * dp;
+            const float s1 = __builtin_amdgcn_fmed3f(dms, dp, 0.0f);
+            const float s2 = __builtin_amdgcn_fmed3f(dm, dps, 0.0f);
+            s = __builtin_amdgcn_fmed3f(s1, s2, copysignf(__builtin_inff(), dp));
+        } else {
+            dps = theta * dp;
+            const float b = 0.5f * (wp - wm);
+            s = __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(dps, dms, 0.0f), b, 0.0f);
+        }
+        dm = dp;
+        dms = dps;
+        return s;
+    }
+}
+
 // ---------------------------------------------------------- Steps 2 to 4
 
 template <int VK, typename R>
@@ -174,18 +204,23 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         return madd(V2, py, V1 * px);
     } else {
         // H = v0 |p| at the four corners (s,t) in {-,+}^2, dH/dp = v0 p/|p|.
-        // |p|^2 is clamped below at the smallest normal number before the
-        // reciprocal square root (v_rsq reads a subnormal as zero): p = 0
-        // still gives H = 0 and speed 0, and gradients below 1e-19 (float)
-        // move with speed v0 p / 1e-19 instead of a full-speed direction.
+        // |p|^2 carries a bias of the smallest normal number, folded into the
+        // fused squares (px^2 + FLT_MIN, then + py^2), so the reciprocal
+        // square root never sees zero or a subnormal (v_rsq reads those as
+        // zero): the speed at p = 0 is 0, gradients below 1e-19 move with
+        // speed v0 p / 1e-19 instead of a full-speed direction, and
+        // H = v0 sqrt(|p|^2 + 2^-126) differs from v0 |p| by at most
+        // |v0| 2^-63 (H(0) = v0 2^-63; a uniform field of it cancels in every
+        // flux difference, so zero densities under a uniform celerity stay
+        // exactly zero).
         constexpr R kTiny = Arith<R>::tiny;
-        const R xm2 = pxm * pxm, xp2 = pxp * pxp;
+        const R xm2 = madd(pxm, pxm, kTiny), xp2 = madd(pxp, pxp, kTiny);
         const R r00 = madd(pym, pym, xm2), r01 = madd(pyp, pyp, xm2);
         const R r10 = madd(pym, pym, xp2), r11 = madd(pyp, pyp, xp2);
-        const R g00 = v0 * Arith<R>::rsq(vmax(r00, kTiny));
-        const R g01 = v0 * Arith<R>::rsq(vmax(r01, kTiny));
-        const R g10 = v0 * Arith<R>::rsq(vmax(r10, kTiny));
-        const R g11 = v0 * Arith<R>::rsq(vmax(r11, kTiny));
+        const R g00 = v0 * Arith<R>::rsq(r00);
+        const R g01 = v0 * Arith<R>::rsq(r01);
+        const R g10 = v0 * Arith<R>::rsq(r10);
+        const R g11 = v0 * Arith<R>::rsq(r11);
         const R H00 = r00 * g00, H01 = r01 * g01, H10 = r10 * g10, H11 = r11 * g11;
         const R hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
         const R hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
@@ -193,9 +228,10 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         // by +-FLT_MIN instead of 0 (two three-operand max/min each).  Then
         // a+ - a- >= 2 FLT_MIN always: where nothing moves along an axis the
         // weights come out as exactly 1/2 (2^-126 * rcp(2^-125)) and the
-        // viscosity as 0 (the product FLT_MIN^2 underflows), which is the
-        // scheme's degenerate case, with no compare or select; a one-sided
-        // speed of 0 becomes 1.2e-38, which moves nothing representable.
+        // viscosity as -FLT_MIN/2, which is the scheme's degenerate case up
+        // to a term below the smallest normal number per unit gradient jump,
+        // with no compare or select; a one-sided speed of 0 becomes 1.2e-38,
+        // which moves nothing representable against normal densities.
         const R ap = vmax(vmax(vmax(vmax(hx00, hx01), hx10), hx11), kTiny);
         const R am = vmin(vmin(vmin(vmin(hx00, hx01), hx10), hx11), -kTiny);
         const R bp = vmax(vmax(vmax(vmax(hy00, hy01), hy10), hy11), kTiny);
@@ -209,9 +245,10 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         const R ia = Arith<R>::rcp(ap - am), ib = Arith<R>::rcp(bp - bm);
         const R wxm = ap * ia, wxp = -am * ia;
         const R wym = bp * ib, wyp = -bm * ib;
-        const R visc_x = ap * am * ia, visc_y = bp * bm * ib;
+        // viscosity a+ a- / (a+ - a-) = -(a+ w+), one product instead of two
+        const R nvx = ap * wxp, nvy = bp * wyp;
         const R sum = madd(wxp, madd(wyp, H11, wym * H10), wxm * madd(wyp, H01, wym * H00));
-        return madd(visc_y, pyp - pym, madd(visc_x, pxp - pxm, sum));
+        return madd(-nvy, pyp - pym, madd(-nvx, pxp - pxm, sum));
     }
 }
 
@@ -395,6 +432,9 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     y[0] = at(row_ptr<S>(s11, k, nx), off);
     sl[1] = limited_slope<LK>(ym2, R(y[7]), R(y[0]), theta);   // slope at edge k0-1/2
     hh[1] = R(0);
+    // float: the carried y difference of the first row and its scaled form
+    float ydm = float(R(y[0]) - R(y[7]));
+    float ydms = LK == LK_SUPERBEE ? 2.0f * ydm : float(theta) * ydm;
 
     // Loads of the first kAhead rows.  kf: row of the next fetch (k0+i+kAhead
     // at iteration i), kf1 the row after it, kfm the row before it.
@@ -442,7 +482,9 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
 
         // Steps 1-2 along y (alpha_11 = -w_y, slopes are odd)
         // (halving is exact, so each face value rounds once, fused or not)
-        const R s0 = limited_slope<LK>(ym1, y0, yp1, theta);
+        R s0;
+        if constexpr (kF64) s0 = limited_slope<LK>(ym1, y0, yp1, theta);
+        else s0 = y_slope_carried<LK>(ym1, y0, yp1, theta, ydm, ydms);
         const R pyp = -madd(R(-0.5), s0, y0);
         const R pym = -madd(R(0.5), sl[hp], ym1);
         sl[h] = s0;
@@ -527,6 +569,18 @@ __device__ __forceinline__ int64_t xcd_tile(int blocks_per_xcd)
 // The first midpoint stage runs the MODE_FWD kernel with half the step:
 // halving is exact in float and double, so the coefficients are those of
 // dt/2.
+// Coupled runs: the step is chosen on the device, so the coefficients come
+// from device memory (one scalar load each, once per wave).
+__device__ __forceinline__ void load_coef(InstDev &I)
+{
+    if (I.coef == nullptr) return;
+    I.dtd = I.coef->dtd;
+    I.cxd = I.coef->cxd;
+    I.cyd = I.coef->cyd;
+    I.cx = I.coef->cx;
+    I.cy = I.coef->cy;
+}
+
 __device__ __forceinline__ void halve_step(InstDev &I)
 {
     I.cx *= 0.5f;
@@ -541,6 +595,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_
 {
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
+    load_coef(I);
     if (half) halve_step(I);
     const int t = (int)tile;
     run_tile<R, S, LK, VK, FIELD, MODE, HSUM>(I, t % I.strips, t / I.strips, threadIdx.x & 63);
@@ -557,6 +612,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
     InstDev I = insts[tile_inst[tile]];
+    load_coef(I);
     if (half) halve_step(I);
     const int local = (int)(tile - I.tile_begin);
     const int strip = local % I.strips, chunk = local / I.strips;

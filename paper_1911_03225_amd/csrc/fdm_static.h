@@ -25,14 +25,19 @@ StaticStatus static_plan_create(const StaticParams &q, hipStream_t s, StaticPlan
 void static_plan_destroy(StaticPlan *p);
 
 // Enqueues tau13 = layer average of sigma13 for densities (a11, a12) and
-// mean stress sigma_bar on s.  a11/a12 are read only; tau13 is written.
-StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, double sigma_bar,
+// the mean stress *sigma_bar (a device double, read when the kernel runs)
+// on s.  a11/a12 are read only; tau13 is written.
+StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, const double *sigma_bar,
                              hipStream_t s, std::string &err);
 
-// As static_plan_run, and also phi (= U^p_13) at the nodes with the given
-// mean, from the same forward transforms.
+// As static_plan_run, and also phi (= U^p_13) at the nodes with the mean
+// *phi_mean (a device double), from the same forward transforms.
 StaticStatus static_plan_run_phi(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
-                                 double sigma_bar, double phi_mean, hipStream_t s, std::string &err);
+                                 const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err);
+
+// Two device doubles owned by the plan, for callers that hold the mean
+// stress and slip on the host (upload them before a run).
+double *static_plan_scalars(StaticPlan *p);
 
 // Celerity at the nodes, written as float32, m = mobility * mfield[i] (mfield
 // may be null):

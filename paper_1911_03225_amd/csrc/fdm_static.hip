@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void layer_multiplier_kernel(T *K, int nx, int
 // two transforms alpha11^ then alpha12^ (interleaved complex).
 template <typename T>
 __global__ __launch_bounds__(256) void green_kernel(const T *spec, T *out, const T *K, const T *d1, const T *d2,
-                                                     int nxh, int ny, T neg_mu_over_n, T sigma_bar)
+                                                     int nxh, int ny, T neg_mu_over_n, const double *sigma_bar)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nmodes = (int64_t)nxh * ny;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void green_kernel(const T *spec, T *out, const
     const T d2r = d2[2 * m2], d2i = d2[2 * m2 + 1];
     T re, im;
     if (idx == 0) {
-        re = sigma_bar;
+        re = (T)*sigma_bar;
         im = T(0);
     } else {
         // conj(d1) a12 - conj(d2) a11
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void velocity_law_kernel(const T *tau, const T
 // transform; spec holds alpha11^ then alpha12^.
 template <typename T>
 __global__ __launch_bounds__(256) void phi_kernel(const T *spec, T *out, const T *d1, const T *d2, int nxh, int ny,
-                                                   T inv_n, T phi_mean)
+                                                   T inv_n, const double *phi_mean)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nmodes = (int64_t)nxh * ny;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void phi_kernel(const T *spec, T *out, const T
     const int m1 = (int)(idx % nxh), m2 = (int)(idx / nxh);
     T re, im;
     if (idx == 0) {
-        re = phi_mean;
+        re = (T)*phi_mean;
         im = T(0);
     } else {
         const T a11r = spec[2 * idx], a11i = spec[2 * idx + 1];
@@ -187,6 +187,7 @@ struct StaticPlan {
     void *K = nullptr;       // ny * nxh reals
     void *d1 = nullptr;      // nxh complex
     void *d2 = nullptr;      // ny complex
+    double *scal = nullptr;  // [mean stress, mean slip] of one-off solves
 };
 
 #define ST_HIP(call)                                                                          \
@@ -212,7 +213,7 @@ void static_plan_destroy(StaticPlan *p)
     if (p->fwd) (void)rocfft_plan_destroy(p->fwd);
     if (p->inv) (void)rocfft_plan_destroy(p->inv);
     if (p->info) (void)rocfft_execution_info_destroy(p->info);
-    for (void *b : {p->work, p->real2, p->spec, p->K, p->d1, p->d2})
+    for (void *b : {p->work, p->real2, p->spec, p->K, p->d1, p->d2, (void *)p->scal})
         if (b) (void)hipFree(b);
     delete p;
 }
@@ -239,6 +240,7 @@ StaticStatus static_plan_create(const StaticParams &q, hipStream_t s, StaticPlan
         ST_HIP(hipMalloc(&p->K, es * nm));
         ST_HIP(hipMalloc(&p->d1, es * 2 * p->nxh));
         ST_HIP(hipMalloc(&p->d2, es * 2 * q.ny));
+        ST_HIP(hipMalloc((void **)&p->scal, 2 * sizeof(double)));
 
         // symbols of the forward differences, in FP64 on the host
         std::vector<double> d1(2 * p->nxh), d2(2 * q.ny);
@@ -328,25 +330,27 @@ StaticStatus static_plan_create(const StaticParams &q, hipStream_t s, StaticPlan
 }
 
 namespace {
-StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi, double sigma_bar,
-                      double phi_mean, hipStream_t s, std::string &err);
+StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
+                      const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err);
 }
 
-StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, double sigma_bar,
+double *static_plan_scalars(StaticPlan *p) { return p->scal; }
+
+StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, const double *sigma_bar,
                              hipStream_t s, std::string &err)
 {
-    return run_impl(p, a11, a12, tau13, nullptr, sigma_bar, 0.0, s, err);
+    return run_impl(p, a11, a12, tau13, nullptr, sigma_bar, nullptr, s, err);
 }
 
 StaticStatus static_plan_run_phi(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
-                                 double sigma_bar, double phi_mean, hipStream_t s, std::string &err)
+                                 const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err)
 {
     return run_impl(p, a11, a12, tau13, phi, sigma_bar, phi_mean, s, err);
 }
 
 namespace {
-StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi, double sigma_bar,
-                      double phi_mean, hipStream_t s, std::string &err)
+StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
+                      const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err)
 {
     const int64_t n = (int64_t)p->nx * p->ny, nm = (int64_t)p->nxh * p->ny;
     ST_FFT(rocfft_execution_info_set_stream(p->info, s));
@@ -367,11 +371,11 @@ StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau
         if (p->f64)
             hipLaunchKernelGGL(phi_kernel<double>, dim3(gb), dim3(256), 0, s, (const double *)p->spec,
                                (double *)p->real2, (const double *)p->d1, (const double *)p->d2, p->nxh, p->ny,
-                               1.0 / (double)n, phi_mean);
+                               1.0 / (double)n, phi_mean);  // device pointer
         else
             hipLaunchKernelGGL(phi_kernel<float>, dim3(gb), dim3(256), 0, s, (const float *)p->spec,
                                (float *)p->real2, (const float *)p->d1, (const float *)p->d2, p->nxh, p->ny,
-                               (float)(1.0 / (double)n), (float)phi_mean);
+                               (float)(1.0 / (double)n), phi_mean);
         ST_HIP(hipGetLastError());
         void *pin[1] = {p->real2}, *pout[1] = {phi};
         ST_FFT(rocfft_execute(p->inv, pin, pout, p->info));
@@ -382,11 +386,11 @@ StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau
     if (p->f64) {
         hipLaunchKernelGGL(green_kernel<double>, dim3(gb), dim3(256), 0, s, (const double *)p->spec, (double *)prod,
                            (const double *)p->K, (const double *)p->d1, (const double *)p->d2, p->nxh, p->ny,
-                           -p->mu / (double)n, sigma_bar);
+                           -p->mu / (double)n, sigma_bar);  // device pointer
     } else {
         hipLaunchKernelGGL(green_kernel<float>, dim3(gb), dim3(256), 0, s, (const float *)p->spec, (float *)prod,
                            (const float *)p->K, (const float *)p->d1, (const float *)p->d2, p->nxh, p->ny,
-                           (float)(-p->mu / (double)n), (float)sigma_bar);
+                           (float)(-p->mu / (double)n), sigma_bar);
     }
     ST_HIP(hipGetLastError());
     void *in2[1] = {prod}, *out2[1] = {tau13};
