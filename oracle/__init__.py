@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "libfdm_oracle.so")
 LIMITERS = ("none", "minmod", "mc", "theta", "superbee")
 _LIM_NONE, _LIM_THETA, _LIM_SUPERBEE = 0, 1, 2
 _LAW, _PRESCRIBED = 0, 1
+SCHEMES = ("semidiscrete", "fully_discrete")
 
 
 def build(force: bool = True) -> str:
@@ -48,7 +49,7 @@ class _Problem(ctypes.Structure):
         ("theta", ctypes.c_double),
         ("v0", ctypes.c_double), ("V1", ctypes.c_double), ("V2", ctypes.c_double),
         ("v0_field", ctypes.c_void_p),
-        ("time_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("time_order", ctypes.c_int32), ("scheme", ctypes.c_int32),
         ("dt", ctypes.c_double),
     ]
 
@@ -82,6 +83,12 @@ def _load():
         lib.orc_run.restype = None
         lib.orc_cfl_dt.argtypes = [P, d]
         lib.orc_cfl_dt.restype = d
+        lib.orc_interp_piece.argtypes = [ctypes.c_int32, d, d, d, d, p, p]
+        lib.orc_interp_piece.restype = None
+        lib.orc_fd_increment_node.argtypes = [P, d, d, d, d, d, d, d, d, d]
+        lib.orc_fd_increment_node.restype = d
+        lib.orc_fd_increment_field.argtypes = [P, p, p, p]
+        lib.orc_fd_increment_field.restype = None
         lib.orc_stats.argtypes = [i64, p, p, p]
         lib.orc_stats.restype = None
         lib.orc_max_threads.argtypes = []
@@ -98,10 +105,13 @@ class Problem:
     limiter: "none" | "minmod" (theta=1) | "mc" (theta=2) | "theta" | "superbee"
     vkind:   "law" (H = v0 |p|) | "prescribed" (H = V . p)
     v0:      uniform celerity, or an (ny, nx) array of node celerities
+    scheme:  "semidiscrete" (Steps 3-4 in the limit dt -> 0, with the
+             integrator time_order) | "fully_discrete" (Steps 1-4 of sec.
+             3.2.3 at the step dt; one pass per step, time_order must be 1)
     """
 
     def __init__(self, nx, ny, dx=1.0, dy=1.0, limiter="minmod", theta=None,
-                 vkind="law", v0=-1.0, V=(0.0, 0.0), time_order=2, dt=None):
+                 vkind="law", v0=-1.0, V=(0.0, 0.0), time_order=2, dt=None, scheme="semidiscrete"):
         self.nx, self.ny = int(nx), int(ny)
         self.dx, self.dy = float(dx), float(dy)
         if limiter not in LIMITERS:
@@ -125,6 +135,11 @@ class Problem:
         self.V = (float(V[0]), float(V[1]))
         self.time_order = int(time_order)
         self.dt = None if dt is None else float(dt)
+        if scheme not in SCHEMES:
+            raise ValueError("unknown scheme %r" % (scheme,))
+        if scheme == "fully_discrete" and self.time_order != 1:
+            raise ValueError("the fully discrete scheme is a one-pass step: time_order must be 1")
+        self.scheme = scheme
 
     def _c(self) -> _Problem:
         lim = {"none": _LIM_NONE, "superbee": _LIM_SUPERBEE}.get(self.limiter, _LIM_THETA)
@@ -136,6 +151,7 @@ class Problem:
         c.v0, c.V1, c.V2 = self.v0, self.V[0], self.V[1]
         c.v0_field = self.v0_field.ctypes.data if self.v0_field is not None else None
         c.time_order = self.time_order
+        c.scheme = SCHEMES.index(self.scheme)
         c.dt = self.dt if self.dt is not None else 0.0
         return c
 
@@ -193,6 +209,34 @@ def stage_rate(prob: Problem, alpha11, alpha12):
     _load().orc_stage_rate(ctypes.byref(c), a11.ctypes.data, a12.ctypes.data,
                            r11.ctypes.data, r12.ctypes.data)
     return r11, r12
+
+
+def interp_piece(side: int, D, Dp, d, h):
+    """Fully discrete Step 1: (increment over phi_j, slope) of the quadratic
+    interpolant piece on the side's interval at x_j + h."""
+    out = (ctypes.c_double * 2)()
+    base = ctypes.addressof(out)
+    _load().orc_interp_piece(int(side), float(D), float(Dp), float(d), float(h), base, base + 8)
+    return out[0], out[1]
+
+
+def fd_increment_node(prob: Problem, wxl, sxl, wxr, sxr, wyd, syd, wyu, syu, v0=None) -> float:
+    """Fully discrete Steps 2-4 at one node: phi^{n+1} - phi^n at step prob.dt."""
+    c = prob._c()
+    return _load().orc_fd_increment_node(ctypes.byref(c), prob.v0 if v0 is None else float(v0),
+                                         *(float(x) for x in (wxl, sxl, wxr, sxr, wyd, syd, wyu, syu)))
+
+
+def fd_increment_field(prob: Problem, alpha11, alpha12) -> np.ndarray:
+    """Node increments phi^{n+1} - phi^n of one fully discrete step."""
+    if prob.dt is None:
+        raise ValueError("Problem.dt must be set (use cfl_dt)")
+    shape = (prob.ny, prob.nx)
+    a11, a12 = _arr(alpha11, shape), _arr(alpha12, shape)
+    out = np.empty(shape)
+    c = prob._c()
+    _load().orc_fd_increment_field(ctypes.byref(c), a11.ctypes.data, a12.ctypes.data, out.ctypes.data)
+    return out
 
 
 def cfl_dt(prob: Problem, nu: float) -> float:

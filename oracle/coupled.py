@@ -21,8 +21,9 @@ case of sec. 3.2.1:
 5. the mean of phi = U^p_13, which the densities do not carry, follows
    phi_{n+1} = phi_n - dt Hhat (Euler), the Heun average of the two stages'
    Hhat, or Hhat of the half-step state (explicit midpoint), so its mean
-   moves by -dt times the mean of that Hhat; the mean strain moves by
-   strain_rate13 * dt.
+   moves by -dt times the mean of that Hhat; with the fully discrete scheme
+   of sec. 3.2.3 it moves by the mean of the node increments.  The mean
+   strain moves by strain_rate13 * dt.
 """
 from __future__ import annotations
 
@@ -47,7 +48,8 @@ def coupled_run(a11, a12, n_steps: int, chunk: int, *, dx: float = 1.0, limiter:
                 theta=None, cfl: float = 0.4, time_order: int = 2, mu: float = 1.0, lam: float = 1.5,
                 layer_h: float = 4.0, cell_l3: float = 512.0, tau0: float = 0.01, mobility: float = 1.0,
                 strain_rate13: float = 1e-3, dt_max: float = 0.05, eps13: float = 0.0, phi_mean: float = 0.0,
-                law: str = "threshold", tau_y: float = 0.0, beta: float = 1.0, mobility_field=None):
+                law: str = "threshold", tau_y: float = 0.0, beta: float = 1.0, mobility_field=None,
+                scheme: str = "semidiscrete"):
     """Returns (alpha11, alpha12, history); history holds one dict per chunk
     (after its last step): t, dt, step, eps13, sigma13, phi_mean, vmax and
     the density sums."""
@@ -68,9 +70,15 @@ def coupled_run(a11, a12, n_steps: int, chunk: int, *, dx: float = 1.0, limiter:
         v0 = v0.astype(np.float32).astype(np.float64)
         vmax = float(np.max(np.abs(v0)))
         dt = round_down_float(min(cfl * dx / vmax, dt_max) if vmax > 0.0 else dt_max)
-        P = T.Problem(nx, ny, dx, dx, limiter=limiter, theta=theta, v0=v0, time_order=time_order, dt=dt)
-        hmean = float(np.mean(T.hhat_field(P, a11, a12)))
-        if time_order == 2:       # Heun: phi - dt/2 (Hhat(u) + Hhat(u + dt L(u)))
+        P = T.Problem(nx, ny, dx, dx, limiter=limiter, theta=theta, v0=v0, time_order=time_order, dt=dt,
+                      scheme=scheme)
+        if scheme == "fully_discrete":   # phi_{n+1} - phi_n: the node increments of the step
+            hmean = -float(np.mean(T.fd_increment_field(P, a11, a12))) / dt
+        else:
+            hmean = float(np.mean(T.hhat_field(P, a11, a12)))
+        if scheme == "fully_discrete":
+            pass
+        elif time_order == 2:       # Heun: phi - dt/2 (Hhat(u) + Hhat(u + dt L(u)))
             Pe = T.Problem(nx, ny, dx, dx, limiter=limiter, theta=theta, v0=v0, time_order=1, dt=dt)
             w11, w12 = T.run(Pe, a11, a12, 1)
             hmean = 0.5 * (hmean + float(np.mean(T.hhat_field(P, w11, w12))))

@@ -50,6 +50,18 @@
  *           paper names for its second-order step, sec. 3.2.2).  The
  *           celerity is frozen over the whole step, as in sec. 3.2.2.
  *
+ * Fully discrete variant (scheme = 1): the steps of sec. 3.2.3 at finite dt,
+ * in phi form at every node: Step 1 the piecewise quadratic interpolant of
+ * eq. (42) along each axis; Step 2 the speeds as above; Step 3 the
+ * interpolant and its slope at the four intermediate points
+ * (x_j + a^+- dt, y_k + b^+- dt), each corrected by -dt H of that slope
+ * (the midpoint-rule solver); Step 4 the projection with the same
+ * tensor-product weights.  The paper defers the 2-D interpolant to another
+ * paper; here it is the separable one, phi_jk + X(x - x_j) + Y(y - y_k) with
+ * X and Y the 1-D pieces of eq. (42) along the node's row and column.  The
+ * node increments phi^{n+1} - phi^n, differenced along x and y, update the
+ * densities; one such step is one time step (no Runge-Kutta stages).
+ *
  * Hamiltonians:  LAW        H = v0 |p|    (eq. 52 / 56), dH/dp = v0 p/|p|,
  *                                          taken as 0 at p = 0;
  *                PRESCRIBED H = V . p     (eq. 28 with only U^p_13 nonzero,
@@ -71,6 +83,7 @@
 
 enum { ORC_LIM_NONE = 0, ORC_LIM_THETA = 1, ORC_LIM_SUPERBEE = 2 };
 enum { ORC_LAW = 0, ORC_PRESCRIBED = 1 };
+enum { ORC_SEMIDISCRETE = 0, ORC_FULLY_DISCRETE = 1 };
 
 typedef struct {
     int64_t nx, ny;          /* pixel nodes along x1 and x2                */
@@ -82,7 +95,7 @@ typedef struct {
     double V1, V2;           /* prescribed velocity                        */
     const double *v0_field;  /* nx*ny celerity at nodes, or NULL           */
     int32_t time_order;      /* 1, 2 (Heun) or 3 (explicit midpoint)       */
-    int32_t reserved;
+    int32_t scheme;          /* ORC_SEMIDISCRETE or ORC_FULLY_DISCRETE     */
     double dt;               /* time step                                  */
 } orc_problem;
 
@@ -275,9 +288,154 @@ void orc_stage_rate(const orc_problem *P, const double *a11, const double *a12,
     free(h);
 }
 
+/* ------------------------------------------- fully discrete scheme (3.2.3) */
+
+/* Step 1: the piece of the quadratic interpolant of eq. (42) that holds
+ * x_j + h, as an increment over phi_j, and its slope there.  side = +1 is the
+ * piece on [x_j, x_{j+1}] (used for the point x_{j+}, h >= 0), side = -1 the
+ * piece on [x_{j-1}, x_j] (the point x_{j-}, h <= 0); the side is explicit so
+ * that h = 0 gives that side's one-sided derivative.  D and Dp are
+ * (Delta phi) and (Delta phi)' of the piece's edge, d the spacing. */
+void orc_interp_piece(int32_t side, double D, double Dp, double d, double h,
+                      double *val, double *slope)
+{
+    if (side > 0) {
+        /* phi_j + D (x - x_j)/d + Dp/(2 d^2) (x - x_j)(x - x_{j+1}), x = x_j + h */
+        *val = D / d * h + Dp / (2.0 * d * d) * h * (h - d);
+        *slope = D / d + Dp / (2.0 * d * d) * ((h - d) + h);
+    } else {
+        /* phi_{j-1} + D (x - x_{j-1})/d + Dp/(2 d^2) (x - x_{j-1})(x - x_j),
+         * with phi_{j-1} = phi_j - D and x - x_{j-1} = d + h */
+        *val = -D + D / d * (d + h) + Dp / (2.0 * d * d) * (d + h) * h;
+        *slope = D / d + Dp / (2.0 * d * d) * (h + (d + h));
+    }
+}
+
+/* Steps 2-4 of the fully discrete scheme at one node: the increment
+ * phi^{n+1}_jk - phi^n_jk.  Inputs: the densities on the four edges around
+ * the node, as w (w_x left and right, w_y below and above), and their limited
+ * slopes in the same units ((Delta phi)' divided by the spacing). */
+double orc_fd_increment_node(const orc_problem *P, double v0,
+                             double wxl, double sxl, double wxr, double sxr,
+                             double wyd, double syd, double wyu, double syu)
+{
+    const double dx = P->dx, dy = P->dy, dt = P->dt;
+    double unused;
+    /* one-sided derivatives (eq. 46 per axis): the pieces' slopes at the node */
+    double px[2], py[2];   /* index 0 is "-", 1 is "+" */
+    orc_interp_piece(-1, dx * wxl, dx * sxl, dx, 0.0, &unused, &px[0]);
+    orc_interp_piece(+1, dx * wxr, dx * sxr, dx, 0.0, &unused, &px[1]);
+    orc_interp_piece(-1, dy * wyd, dy * syd, dy, 0.0, &unused, &py[0]);
+    orc_interp_piece(+1, dy * wyu, dy * syu, dy, 0.0, &unused, &py[1]);
+
+    /* Step 2: one-sided local speeds over the four combinations (eq. 53). */
+    double ap = 0.0, am = 0.0, bp = 0.0, bm = 0.0;
+    for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) {
+            double H, Hx, Hy;
+            orc_hamiltonian(P, v0, px[s], py[t], &H, &Hx, &Hy);
+            if (Hx > ap) ap = Hx;
+            if (Hx < am) am = Hx;
+            if (Hy > bp) bp = Hy;
+            if (Hy < bm) bm = Hy;
+        }
+
+    /* Step 3: interpolant and slope at x_{j-+} = x_j + a^-+ dt and
+     * y_{k-+} = y_k + b^-+ dt (separable: the x piece along the row, the y
+     * piece along the column). */
+    double X[2], Xs[2], Y[2], Ys[2];
+    orc_interp_piece(-1, dx * wxl, dx * sxl, dx, am * dt, &X[0], &Xs[0]);
+    orc_interp_piece(+1, dx * wxr, dx * sxr, dx, ap * dt, &X[1], &Xs[1]);
+    orc_interp_piece(-1, dy * wyd, dy * syd, dy, bm * dt, &Y[0], &Ys[0]);
+    orc_interp_piece(+1, dy * wyu, dy * syu, dy, bp * dt, &Y[1], &Ys[1]);
+
+    /* Step 4: projection onto the node, weights a+/(a+ - a-) for the "-"
+     * point and -a-/(a+ - a-) for the "+" point along each axis, 1/2 each
+     * when nothing moves along that axis. */
+    double wx[2], wy[2];
+    if (ap - am > 0.0) {
+        wx[0] = ap / (ap - am);
+        wx[1] = -am / (ap - am);
+    } else {
+        wx[0] = 0.5;
+        wx[1] = 0.5;
+    }
+    if (bp - bm > 0.0) {
+        wy[0] = bp / (bp - bm);
+        wy[1] = -bm / (bp - bm);
+    } else {
+        wy[0] = 0.5;
+        wy[1] = 0.5;
+    }
+    double inc = 0.0;
+    for (int s = 0; s < 2; ++s)
+        for (int t = 0; t < 2; ++t) {
+            double H, Hx, Hy;
+            orc_hamiltonian(P, v0, Xs[s], Ys[t], &H, &Hx, &Hy);
+            const double phi_st = (X[s] + Y[t]) - dt * H;   /* phi^{n+1}_{j s, k t} - phi_jk */
+            inc += wx[s] * wy[t] * phi_st;
+        }
+    return inc;
+}
+
+/* Node increments phi^{n+1} - phi^n of the fully discrete scheme at every
+ * node (Steps 1-4); inc has nx*ny entries. */
+void orc_fd_increment_field(const orc_problem *P, const double *a11, const double *a12, double *inc)
+{
+    const int64_t nx = P->nx, ny = P->ny;
+    double *sx = (double *)malloc(sizeof(double) * nx * ny);
+    double *sy = (double *)malloc(sizeof(double) * nx * ny);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ny; ++k) {
+        for (int64_t j = 0; j < nx; ++j) {
+            sx[k * nx + j] = orc_slope(P->limiter, P->theta, a12[k * nx + wrap(j - 1, nx)], a12[k * nx + j],
+                                       a12[k * nx + wrap(j + 1, nx)]);
+            sy[k * nx + j] = orc_slope(P->limiter, P->theta, -a11[wrap(k - 1, ny) * nx + j], -a11[k * nx + j],
+                                       -a11[wrap(k + 1, ny) * nx + j]);
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ny; ++k) {
+        for (int64_t j = 0; j < nx; ++j) {
+            int64_t e_right = k * nx + j, e_left = k * nx + wrap(j - 1, nx);
+            int64_t f_up = k * nx + j, f_down = wrap(k - 1, ny) * nx + j;
+            double v0 = P->v0_field ? P->v0_field[k * nx + j] : P->v0;
+            inc[k * nx + j] = orc_fd_increment_node(P, v0, a12[e_left], sx[e_left], a12[e_right], sx[e_right],
+                                                    -a11[f_down], sy[f_down], -a11[f_up], sy[f_up]);
+        }
+    }
+    free(sx);
+    free(sy);
+}
+
+/* One fully discrete step in place: w_x(j+1/2) += (inc_{j+1} - inc_j)/dx and
+ * w_y(k+1/2) += (inc_{k+1} - inc_k)/dy, i.e. the new densities are the
+ * differences of phi^{n+1}. */
+static void fd_step(const orc_problem *P, double *a11, double *a12)
+{
+    const int64_t nx = P->nx, ny = P->ny;
+    double *inc = (double *)malloc(sizeof(double) * nx * ny);
+    orc_fd_increment_field(P, a11, a12, inc);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ny; ++k) {
+        for (int64_t j = 0; j < nx; ++j) {
+            double d0 = inc[k * nx + j];
+            double dxp = inc[k * nx + wrap(j + 1, nx)];
+            double dyp = inc[wrap(k + 1, ny) * nx + j];
+            a12[k * nx + j] = a12[k * nx + j] + (dxp - d0) / P->dx;
+            a11[k * nx + j] = a11[k * nx + j] - (dyp - d0) / P->dy;
+        }
+    }
+    free(inc);
+}
+
 /* One time step in place. */
 void orc_step(const orc_problem *P, double *a11, double *a12)
 {
+    if (P->scheme == ORC_FULLY_DISCRETE) {
+        fd_step(P, a11, a12);
+        return;
+    }
     const int64_t n = P->nx * P->ny;
     const double dt = P->dt;
     double *r11 = (double *)malloc(sizeof(double) * n);

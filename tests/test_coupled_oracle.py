@@ -115,3 +115,40 @@ def test_obstacles_do_not_move():
     assert ex.sum() > 100
     assert np.array_equal(b12[ex], a12[ex]) and np.array_equal(b11[ey], a11[ey])
     assert not np.array_equal(b12, a12)
+
+
+def test_fully_discrete_slip_matches_the_phi_form():
+    """Fully discrete scheme: phi itself advanced by the node increments has
+    the transported densities as differences and the tracked mean slip as
+    mean; without a limiter the run equals the one-stage semi-discrete run."""
+    phi, _, _ = _rings(seed=6)
+    ph = phi.copy()
+    a12 = np.roll(ph, -1, axis=1) - ph
+    a11 = -(np.roll(ph, -1, axis=0) - ph)
+    kw = dict(KW, time_order=1, limiter="mc")
+    eps, pm = 0.02, float(phi.mean())
+    ny, nx = a11.shape
+    c11, c12 = a11.copy(), a12.copy()
+    for _ in range(6):
+        tau = S.static_tau13(c11, c12, 1.0, 1.0, 1.0, 1.5, 3, 24, eps, pm)
+        v0 = (-CP.soft_threshold(tau, 0.005)).astype(np.float32).astype(np.float64)
+        vmax = np.max(np.abs(v0))
+        dt = CP.round_down_float(min(0.4 / vmax, KW["dt_max"]) if vmax > 0 else KW["dt_max"])
+        P = T.Problem(nx, ny, limiter="mc", v0=v0, time_order=1, dt=dt, scheme="fully_discrete")
+        inc = T.fd_increment_field(P, c11, c12)
+        ph = ph + inc
+        c11, c12 = T.run(P, c11, c12, 1)
+        pm += inc.mean()
+        eps += KW["strain_rate13"] * dt
+    d12 = np.roll(ph, -1, axis=1) - ph
+    d11 = -(np.roll(ph, -1, axis=0) - ph)
+    assert np.max(np.abs(d12 - c12)) < 1e-13 and np.max(np.abs(d11 - c11)) < 1e-13
+    b11, b12, hist = CP.coupled_run(a11, a12, 6, 6, tau0=0.005, eps13=0.02, phi_mean=float(phi.mean()),
+                                    scheme="fully_discrete", **kw)
+    assert np.array_equal(b11, c11) and np.array_equal(b12, c12)
+    assert hist[-1]["phi_mean"] == pytest.approx(pm, abs=1e-14)
+    kn = dict(kw, limiter="none")
+    f = CP.coupled_run(a11, a12, 6, 6, tau0=0.005, eps13=0.02, phi_mean=pm, scheme="fully_discrete", **kn)
+    e = CP.coupled_run(a11, a12, 6, 6, tau0=0.005, eps13=0.02, phi_mean=pm, **kn)
+    assert np.max(np.abs(f[0] - e[0])) < 1e-13 and np.max(np.abs(f[1] - e[1])) < 1e-13
+    assert f[2][-1]["phi_mean"] == pytest.approx(e[2][-1]["phi_mean"], abs=1e-13)
