@@ -26,6 +26,7 @@ struct fdm_ctx {
     hipStream_t capture = nullptr;          // private stream for graph capture
     int32_t n = 0;
     int32_t time_order = 2;
+    bool fd = false;   // fully discrete scheme (one pass per step)
     int32_t schedule = FDM_SCHEDULE_AUTO;
     int32_t precision = FDM_PRECISION_FP32;
     bool batched = false;
@@ -108,6 +109,9 @@ std::string check_desc(const fdm_transport_desc &d)
     if (d.limiter == FDM_LIMITER_THETA && !(d.theta >= 1.0 && d.theta <= 2.0))
         return "theta must lie in [1, 2]";
     if (d.time_order < 0 || d.time_order > 3) return "time_order must be 1, 2 or 3";
+    if (d.scheme != FDM_SCHEME_SEMIDISCRETE && d.scheme != FDM_SCHEME_FULLY_DISCRETE) return "unknown scheme";
+    if (d.scheme == FDM_SCHEME_FULLY_DISCRETE && d.time_order > 1)
+        return "the fully discrete scheme is one pass per step: time_order must be 0 or 1";
     if (!(std::isfinite(d.dt) && d.dt >= 0.0)) return "dt must be finite and >= 0";
     if (d.dt == 0.0 && !(d.cfl > 0.0 && d.cfl <= 1.0)) return "cfl must lie in (0, 1]";
     if (d.velocity != FDM_VELOCITY_LAW && d.velocity != FDM_VELOCITY_PRESCRIBED)
@@ -261,7 +265,7 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
         }
         for (int m = 0; m < nm; ++m) {
             if (c->batched) {
-                FDM_HIP(c, fdm::launch_stage_batched(c->d_inst, c->d_tile_inst, c->total_tiles, modes[m],
+                FDM_HIP(c, fdm::launch_stage_batched(c->d_inst, c->d_tile_inst, c->total_tiles, modes[m], c->fd,
                                                      c->precision, s));
             } else {
                 for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_stage(c->inst[i], modes[m], c->precision, s));
@@ -529,9 +533,12 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     for (int i = 0; i < n_instances; ++i) {
         const std::string m = check_desc(descs[i]);
         if (!m.empty()) return fail(nullptr, FDM_ERR_INVALID_ARG, "descriptor " + std::to_string(i) + ": " + m);
-        const int32_t o = descs[i].time_order == 0 ? 2 : descs[i].time_order;
+        const bool fd = descs[i].scheme == FDM_SCHEME_FULLY_DISCRETE;
+        const int32_t o = descs[i].time_order == 0 ? (fd ? 1 : 2) : descs[i].time_order;
         if (order >= 0 && o != order)
             return fail(nullptr, FDM_ERR_INVALID_ARG, "all instances of a context must share time_order");
+        if (descs[i].scheme != descs[0].scheme)
+            return fail(nullptr, FDM_ERR_INVALID_ARG, "all instances of a context must share the scheme");
         order = o;
     }
     // Courant bound of a fixed dt needs s_max; uniform cases are checked here,
@@ -541,6 +548,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     c->stream = (hipStream_t)hip_stream;
     c->n = n_instances;
     c->time_order = order;
+    c->fd = descs[0].scheme == FDM_SCHEME_FULLY_DISCRETE;
     c->schedule = opt.schedule;
     c->precision = opt.precision;
     c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN;
@@ -634,7 +642,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         I.cy = (float)I.cyd;
         I.theta = (float)I.thetad;
         I.limiter = d.limiter;
-        I.vkind = d.velocity;
+        I.vkind = d.velocity | (d.scheme == FDM_SCHEME_FULLY_DISCRETE ? fdm::VK_FD : 0);
     }
     c->dt_last = c->dt;
     {

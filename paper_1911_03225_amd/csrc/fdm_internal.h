@@ -18,7 +18,9 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 
 // Limiter and Hamiltonian codes (values of the public enums).
 enum : int { LIM_NONE = 0, LIM_MINMOD = 1, LIM_MC = 2, LIM_THETA = 3, LIM_SUPERBEE = 4 };
-enum : int { VK_LAW = 0, VK_PRESCRIBED = 1 };
+// Hamiltonian kind (bit 0: LAW or PRESCRIBED) and scheme (bit 1: the fully
+// discrete scheme of sec. 3.2.3 instead of its dt -> 0 limit).
+enum : int { VK_LAW = 0, VK_PRESCRIBED = 1, VK_FD = 2, VK_LAW_FD = 2, VK_PRESCRIBED_FD = 3 };
 
 // What one stage launch reads and writes.
 //   MODE_FWD   : w = a + dt L(a)                 (first stage / Euler step)
@@ -78,8 +80,9 @@ struct StatsPartial {
 constexpr int kStatsBlocks = 512;   // fixed => deterministic reduction order
 
 hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s);
+// fd: the instances use the fully discrete scheme (all or none of a batch)
 hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst,
-                                int64_t total_tiles, int mode, int precision, hipStream_t s);
+                                int64_t total_tiles, int mode, bool fd, int precision, hipStream_t s);
 hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s);
 hipError_t launch_stats(const void *a11, const void *a12, int64_t n, int precision,
                         StatsPartial *d_partials, double *d_out, hipStream_t s);

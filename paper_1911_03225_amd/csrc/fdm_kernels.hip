@@ -7,10 +7,10 @@ namespace fdm {
 
 hipError_t launch_stage_f32(const InstDev &I, int mode, hipStream_t s);
 hipError_t launch_stage_batched_f32(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
-                                    int mode, hipStream_t s);
+                                    int mode, bool fd, hipStream_t s);
 hipError_t launch_stage_f64(const InstDev &I, int mode, bool f64_state, hipStream_t s);
 hipError_t launch_stage_batched_f64(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
-                                    int mode, bool f64_state, hipStream_t s);
+                                    int mode, bool fd, bool f64_state, hipStream_t s);
 
 hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s)
 {
@@ -19,10 +19,10 @@ hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s
 }
 
 hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
-                                int mode, int precision, hipStream_t s)
+                                int mode, bool fd, int precision, hipStream_t s)
 {
-    if (precision == PREC_FP32) return launch_stage_batched_f32(d_inst, d_tile_inst, total_tiles, mode, s);
-    return launch_stage_batched_f64(d_inst, d_tile_inst, total_tiles, mode, precision == PREC_FP64, s);
+    if (precision == PREC_FP32) return launch_stage_batched_f32(d_inst, d_tile_inst, total_tiles, mode, fd, s);
+    return launch_stage_batched_f64(d_inst, d_tile_inst, total_tiles, mode, fd, precision == PREC_FP64, s);
 }
 
 namespace {

@@ -322,6 +322,133 @@ __device__ __forceinline__ double numerical_hamiltonian_ieee(double pxm, double 
     }
 }
 
+// Fully discrete scheme (sec. 3.2.3), float.  With the separable quadratic
+// interpolant the value over phi_jk at the corner (x_j + a^s dt, y_k + b^t dt)
+// is X_s + Y_t, X_s = dt a^s (p_x^s + a^s dt sx^s / (2 dx)), and its slope is
+// q_x^s = p_x^s + a^s (dt/dx) sx^s (likewise along y).  Projecting
+// X_s + Y_t - dt H(q^s, q^t) with the weights and dividing by -dt gives the
+// node's rate in the same units as the semi-discrete Hhat:
+//   Hhat_fd = sum_st w_s v_t H(q_x^s, q_y^t)
+//           + a+a-/(a+ - a-) [(p_x^+ - p_x^-) + (dt/dx)/2 (a+ sx^+ - a- sx^-)]
+//           + the same along y,
+// because w_+ a+ = -a+a-/(a+ - a-) = -w_- a-.  sx^+- are the limited slopes
+// (in density units) of the edges right/left of the node, sy^+- above/below;
+// cx = dt/dx, cy = dt/dy.  The speeds and weights are those of the
+// semi-discrete scheme (same FLT_MIN bounds); |q| uses the hardware square
+// root (|q| = 0 gives H = 0).
+template <int VH>
+__device__ __forceinline__ float fd_hamiltonian(float pxm, float pxp, float pym, float pyp, float sxm, float sxp,
+                                                float sym, float syp, float v0, float V1, float V2, float cx,
+                                                float cy)
+{
+    float ap, am, bp, bm;
+    if constexpr (VH == VK_PRESCRIBED) {
+        ap = vmax(V1, Arith<float>::tiny);
+        am = vmin(V1, -Arith<float>::tiny);
+        bp = vmax(V2, Arith<float>::tiny);
+        bm = vmin(V2, -Arith<float>::tiny);
+    } else {
+        constexpr float kTiny = Arith<float>::tiny;
+        const float xm2 = madd(pxm, pxm, kTiny), xp2 = madd(pxp, pxp, kTiny);
+        const float g00 = v0 * Arith<float>::rsq(madd(pym, pym, xm2));
+        const float g01 = v0 * Arith<float>::rsq(madd(pyp, pyp, xm2));
+        const float g10 = v0 * Arith<float>::rsq(madd(pym, pym, xp2));
+        const float g11 = v0 * Arith<float>::rsq(madd(pyp, pyp, xp2));
+        const float hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
+        const float hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
+        ap = vmax(vmax(vmax(vmax(hx00, hx01), hx10), hx11), kTiny);
+        am = vmin(vmin(vmin(vmin(hx00, hx01), hx10), hx11), -kTiny);
+        bp = vmax(vmax(vmax(vmax(hy00, hy01), hy10), hy11), kTiny);
+        bm = vmin(vmin(vmin(vmin(hy00, hy01), hy10), hy11), -kTiny);
+    }
+    // slopes of the interpolant at the intermediate points
+    const float qxm = madd(cx * am, sxm, pxm), qxp = madd(cx * ap, sxp, pxp);
+    const float qym = madd(cy * bm, sym, pym), qyp = madd(cy * bp, syp, pyp);
+    float H00, H01, H10, H11;
+    if constexpr (VH == VK_PRESCRIBED) {
+        H00 = madd(V2, qym, V1 * qxm);
+        H01 = madd(V2, qyp, V1 * qxm);
+        H10 = madd(V2, qym, V1 * qxp);
+        H11 = madd(V2, qyp, V1 * qxp);
+    } else {
+        const float xm2 = qxm * qxm, xp2 = qxp * qxp;
+        H00 = v0 * __builtin_amdgcn_sqrtf(madd(qym, qym, xm2));
+        H01 = v0 * __builtin_amdgcn_sqrtf(madd(qyp, qyp, xm2));
+        H10 = v0 * __builtin_amdgcn_sqrtf(madd(qym, qym, xp2));
+        H11 = v0 * __builtin_amdgcn_sqrtf(madd(qyp, qyp, xp2));
+    }
+    const float ia = Arith<float>::rcp(ap - am), ib = Arith<float>::rcp(bp - bm);
+    const float wxm = ap * ia, wxp = -am * ia;
+    const float wym = bp * ib, wyp = -bm * ib;
+    const float nvx = ap * wxp, nvy = bp * wyp;   // minus the viscosities
+    const float corr_x = madd(0.5f * cx, madd(ap, sxp, -(am * sxm)), pxp - pxm);
+    const float corr_y = madd(0.5f * cy, madd(bp, syp, -(bm * sym)), pyp - pym);
+    const float sum = madd(wxp, madd(wyp, H11, wym * H10), wxm * madd(wyp, H01, wym * H00));
+    return madd(-nvy, corr_y, madd(-nvx, corr_x, sum));
+}
+
+// Fully discrete scheme, FP64 modes: the same quantities with IEEE
+// operations in the order of the definition (speeds and weights as in
+// numerical_hamiltonian_ieee, |q| = sqrt(qx^2 + qy^2)).
+template <int VH>
+__device__ __forceinline__ double fd_hamiltonian_ieee(double pxm, double pxp, double pym, double pyp, double sxm,
+                                                      double sxp, double sym, double syp, double v0, double V1,
+                                                      double V2, double cx, double cy)
+{
+    const double px[2] = {pxm, pxp}, py[2] = {pym, pyp};
+    double ap = 0.0, am = 0.0, bp = 0.0, bm = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            double hx, hy;
+            if constexpr (VH == VK_PRESCRIBED) {
+                hx = V1;
+                hy = V2;
+            } else {
+                const double r = sqrt(px[s] * px[s] + py[t] * py[t]);
+                hx = r > 0.0 ? v0 * px[s] / r : 0.0;
+                hy = r > 0.0 ? v0 * py[t] / r : 0.0;
+            }
+            ap = hx > ap ? hx : ap;
+            am = hx < am ? hx : am;
+            bp = hy > bp ? hy : bp;
+            bm = hy < bm ? hy : bm;
+        }
+    const double qx[2] = {pxm + cx * am * sxm, pxp + cx * ap * sxp};
+    const double qy[2] = {pym + cy * bm * sym, pyp + cy * bp * syp};
+    double wx[2], wy[2], visc_x, visc_y;
+    if (ap - am > 0.0) {
+        wx[0] = ap / (ap - am);
+        wx[1] = -am / (ap - am);
+        visc_x = ap * am / (ap - am);
+    } else {
+        wx[0] = 0.5;
+        wx[1] = 0.5;
+        visc_x = 0.0;
+    }
+    if (bp - bm > 0.0) {
+        wy[0] = bp / (bp - bm);
+        wy[1] = -bm / (bp - bm);
+        visc_y = bp * bm / (bp - bm);
+    } else {
+        wy[0] = 0.5;
+        wy[1] = 0.5;
+        visc_y = 0.0;
+    }
+    double hhat = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const double H = VH == VK_PRESCRIBED ? V1 * qx[s] + V2 * qy[t] : v0 * sqrt(qx[s] * qx[s] + qy[t] * qy[t]);
+            hhat += wx[s] * wy[t] * H;
+        }
+    hhat += visc_x * ((pxp - pxm) + 0.5 * cx * (ap * sxp - am * sxm));
+    hhat += visc_y * ((pyp - pym) + 0.5 * cy * (bp * syp - bm * sym));
+    return hhat;
+}
+
 __device__ __forceinline__ int next_row(int k, int ny)
 {
     k += 1;
@@ -389,6 +516,8 @@ template <typename R, typename S, int LK, int VK, bool FIELD, int MODE, bool HSU
 __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
 {
     constexpr bool kF64 = sizeof(R) == 8;
+    constexpr bool kFD = (VK & VK_FD) != 0;   // fully discrete scheme
+    constexpr int VH = VK & 1;                // the Hamiltonian
     constexpr bool kBase = MODE == MODE_HEUN2 || MODE == MODE_MID2;   // also reads the base state
     const int nx = I.nx, ny = I.ny;
     const void *s12 = MODE == MODE_FWD ? I.a12 : I.w12;
@@ -495,10 +624,19 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         const R pxm = from_left(madd(R(0.5), sx, wx));
         // Steps 2-4
         R hv;
-        if constexpr (kF64)
-            hv = numerical_hamiltonian_ieee<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
-        else
-            hv = numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
+        if constexpr (kFD) {
+            // slopes in density units: x from this lane (edge j+1/2) and the
+            // left one; y of w_y = -alpha_11 above (k+1/2) and below (k-1/2)
+            const R sxm = from_left(sx);
+            if constexpr (kF64)
+                hv = fd_hamiltonian_ieee<VH>(pxm, pxp, pym, pyp, sxm, sx, -sl[hp], -s0, v0, V1, V2, cx, cy);
+            else
+                hv = fd_hamiltonian<VH>(pxm, pxp, pym, pyp, sxm, sx, -sl[hp], -s0, v0, V1, V2, cx, cy);
+        } else if constexpr (kF64) {
+            hv = numerical_hamiltonian_ieee<VH>(pxm, pxp, pym, pyp, v0, V1, V2);
+        } else {
+            hv = numerical_hamiltonian<VH>(pxm, pxp, pym, pyp, v0, V1, V2);
+        }
         const R hr = from_right(hv);
         const R hprev = hh[hp];
         hh[h] = hv;
@@ -604,7 +742,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_
 // Batched: one launch for every tile of every instance; tile_inst maps a
 // global tile to its instance.  Limiter, Hamiltonian and field presence are
 // per instance and uniform over a wave.
-template <typename R, typename S, int MODE>
+template <typename R, typename S, int MODE, bool FD>
 __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__restrict__ insts,
                                                                const int32_t *__restrict__ tile_inst,
                                                                int64_t total_tiles, int blocks_per_xcd, int half)
@@ -618,7 +756,26 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__
     const int strip = local % I.strips, chunk = local / I.strips;
     const int lane = threadIdx.x & 63;
     const int lk = limiter_kind(I.limiter);
-    if (I.vkind == VK_PRESCRIBED) {
+    if constexpr (FD) {
+        if (I.vkind == VK_PRESCRIBED_FD) {
+            if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane);
+            else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane);
+            else run_tile<R, S, LK_THETA, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane);
+            return;
+        }
+        if (I.vkind == VK_LAW_FD) {
+            if (I.v0f != nullptr) {
+                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane);
+                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane);
+                else run_tile<R, S, LK_THETA, VK_LAW_FD, true, MODE>(I, strip, chunk, lane);
+            } else {
+                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane);
+                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane);
+                else run_tile<R, S, LK_THETA, VK_LAW_FD, false, MODE>(I, strip, chunk, lane);
+            }
+        }
+        return;
+    } else if (I.vkind == VK_PRESCRIBED) {
         if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
         else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
         else run_tile<R, S, LK_THETA, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
@@ -640,25 +797,62 @@ hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
     const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
-    if (mode == MODE_FWD || mode == MODE_MID1)
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_FWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd,
-                           mode == MODE_MID1 ? 1 : 0);
-    else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_BWD, HSUM>), grid, block, 0, s, I, tiles, per_xcd,
-                           0);
-    else if (mode == MODE_MID2)
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_MID2, HSUM>), grid, block, 0, s, I, tiles, per_xcd,
-                           0);
-    else
-        hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_HEUN2, HSUM>), grid, block, 0, s, I, tiles,
-                           per_xcd, 0);
+    if constexpr ((VK & VK_FD) != 0) {   // one pass per step: forward and backward ping-pong only
+        if (mode == MODE_FWD)
+            hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_FWD, HSUM>), grid, block, 0, s, I, tiles,
+                               per_xcd, 0);
+        else if (mode == MODE_BWD)
+            hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_BWD, HSUM>), grid, block, 0, s, I, tiles,
+                               per_xcd, 0);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        if (mode == MODE_FWD || mode == MODE_MID1)
+            hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_FWD, HSUM>), grid, block, 0, s, I, tiles,
+                               per_xcd, mode == MODE_MID1 ? 1 : 0);
+        else if (mode == MODE_BWD)
+            hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_BWD, HSUM>), grid, block, 0, s, I, tiles,
+                               per_xcd, 0);
+        else if (mode == MODE_MID2)
+            hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_MID2, HSUM>), grid, block, 0, s, I, tiles,
+                               per_xcd, 0);
+        else
+            hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_HEUN2, HSUM>), grid, block, 0, s, I, tiles,
+                               per_xcd, 0);
+    }
     return hipGetLastError();
+}
+
+// The fully discrete scheme: the same dispatch over the VK_FD kinds.
+template <typename R, typename S>
+hipError_t launch_stage_fd(const InstDev &I, int mode, hipStream_t s)
+{
+    const int lk = limiter_kind(I.limiter);
+    if (I.vkind == VK_PRESCRIBED_FD) {
+        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_PRESCRIBED_FD, false>(I, mode, s);
+        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_PRESCRIBED_FD, false>(I, mode, s);
+        return launch_stage_t<R, S, LK_THETA, VK_PRESCRIBED_FD, false>(I, mode, s);
+    }
+    if (I.v0f != nullptr && I.hsum != nullptr) {
+        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW_FD, true, true>(I, mode, s);
+        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW_FD, true, true>(I, mode, s);
+        return launch_stage_t<R, S, LK_THETA, VK_LAW_FD, true, true>(I, mode, s);
+    }
+    if (I.v0f != nullptr) {
+        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW_FD, true>(I, mode, s);
+        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW_FD, true>(I, mode, s);
+        return launch_stage_t<R, S, LK_THETA, VK_LAW_FD, true>(I, mode, s);
+    }
+    if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW_FD, false>(I, mode, s);
+    if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW_FD, false>(I, mode, s);
+    return launch_stage_t<R, S, LK_THETA, VK_LAW_FD, false>(I, mode, s);
 }
 
 template <typename R, typename S>
 hipError_t launch_stage_r(const InstDev &I, int mode, hipStream_t s)
 {
     const int lk = limiter_kind(I.limiter);
+    if ((I.vkind & VK_FD) != 0) return launch_stage_fd<R, S>(I, mode, s);
     if (I.vkind == VK_PRESCRIBED) {
         if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_PRESCRIBED, false>(I, mode, s);
         if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_PRESCRIBED, false>(I, mode, s);
@@ -681,22 +875,33 @@ hipError_t launch_stage_r(const InstDev &I, int mode, hipStream_t s)
 
 template <typename R, typename S>
 hipError_t launch_batched_r(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles, int mode,
-                            hipStream_t s)
+                            bool fd, hipStream_t s)
 {
     const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
+    if (fd) {   // its own kernels, so the semi-discrete ones keep their register budget
+        if (mode == MODE_FWD)
+            hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_FWD, true>), grid, block, 0, s, d_inst, d_tile_inst,
+                               total_tiles, per_xcd, 0);
+        else if (mode == MODE_BWD)
+            hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_BWD, true>), grid, block, 0, s, d_inst, d_tile_inst,
+                               total_tiles, per_xcd, 0);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (mode == MODE_FWD || mode == MODE_MID1)
-        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_FWD>), grid, block, 0, s, d_inst, d_tile_inst,
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_FWD, false>), grid, block, 0, s, d_inst, d_tile_inst,
                            total_tiles, per_xcd, mode == MODE_MID1 ? 1 : 0);
     else if (mode == MODE_BWD)
-        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_BWD>), grid, block, 0, s, d_inst, d_tile_inst,
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_BWD, false>), grid, block, 0, s, d_inst, d_tile_inst,
                            total_tiles, per_xcd, 0);
     else if (mode == MODE_MID2)
-        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_MID2>), grid, block, 0, s, d_inst, d_tile_inst,
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_MID2, false>), grid, block, 0, s, d_inst, d_tile_inst,
                            total_tiles, per_xcd, 0);
     else
-        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_HEUN2>), grid, block, 0, s, d_inst, d_tile_inst,
+        hipLaunchKernelGGL((stage_kernel_batched<R, S, MODE_HEUN2, false>), grid, block, 0, s, d_inst, d_tile_inst,
                            total_tiles, per_xcd, 0);
     return hipGetLastError();
 }

@@ -16,9 +16,9 @@ hipError_t launch_stage_f32(const InstDev &I, int mode, hipStream_t s)
 }
 
 hipError_t launch_stage_batched_f32(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
-                                    int mode, hipStream_t s)
+                                    int mode, bool fd, hipStream_t s)
 {
-    return launch_batched_r<float, float>(d_inst, d_tile_inst, total_tiles, mode, s);
+    return launch_batched_r<float, float>(d_inst, d_tile_inst, total_tiles, mode, fd, s);
 }
 
 }  // namespace fdm

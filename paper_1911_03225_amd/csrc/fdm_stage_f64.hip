@@ -17,10 +17,10 @@ hipError_t launch_stage_f64(const InstDev &I, int mode, bool f64_state, hipStrea
 }
 
 hipError_t launch_stage_batched_f64(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
-                                    int mode, bool f64_state, hipStream_t s)
+                                    int mode, bool fd, bool f64_state, hipStream_t s)
 {
-    return f64_state ? launch_batched_r<double, double>(d_inst, d_tile_inst, total_tiles, mode, s)
-                     : launch_batched_r<double, float>(d_inst, d_tile_inst, total_tiles, mode, s);
+    return f64_state ? launch_batched_r<double, double>(d_inst, d_tile_inst, total_tiles, mode, fd, s)
+                     : launch_batched_r<double, float>(d_inst, d_tile_inst, total_tiles, mode, fd, s);
 }
 
 }  // namespace fdm

@@ -24,13 +24,14 @@ LIMITERS = {"none": 0, "minmod": 1, "mc": 2, "theta": 3, "superbee": 4}
 VELOCITIES = {"law": 0, "prescribed": 1}
 SCHEDULES = {"auto": 0, "batched": 1, "plain": 2}
 PRECISIONS = {"fp32": 0, "fp64_arith": 1, "fp64": 2}
+SCHEMES = {"semidiscrete": 0, "fully_discrete": 1}
 
 
 class fdm_transport_desc(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("dx", ctypes.c_double), ("dy", ctypes.c_double),
-        ("limiter", ctypes.c_int32), ("theta", ctypes.c_double),
+        ("limiter", ctypes.c_int32), ("scheme", ctypes.c_int32), ("theta", ctypes.c_double),
         ("time_order", ctypes.c_int32), ("cfl", ctypes.c_double), ("dt", ctypes.c_double),
         ("velocity", ctypes.c_int32), ("v0", ctypes.c_double),
         ("v0_field", ctypes.c_void_p), ("V", ctypes.c_double * 2),
@@ -163,11 +164,13 @@ def _check(status: int, where: str, ctx=None):
 
 
 def desc(nx, ny, dx=1.0, dy=1.0, limiter="minmod", theta=1.0, time_order=2, cfl=0.4,
-         dt=0.0, velocity="law", v0=-1.0, v0_field=None, V=(0.0, 0.0)) -> fdm_transport_desc:
+         dt=0.0, velocity="law", v0=-1.0, v0_field=None, V=(0.0, 0.0),
+         scheme="semidiscrete") -> fdm_transport_desc:
     """Build an fdm_transport_desc; v0_field is a float32 CUDA tensor of shape (ny, nx)."""
     d = fdm_transport_desc()
     d.nx, d.ny, d.dx, d.dy = int(nx), int(ny), float(dx), float(dy)
     d.limiter = LIMITERS[limiter] if isinstance(limiter, str) else int(limiter)
+    d.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     d.theta, d.time_order, d.cfl, d.dt = float(theta), int(time_order), float(cfl), float(dt)
     d.velocity = VELOCITIES[velocity] if isinstance(velocity, str) else int(velocity)
     d.v0 = float(v0)

@@ -45,11 +45,12 @@ def gpu_run(a11, a12, n_steps, snapshots=None, options=None, **desc_kw):
 
 
 def oracle_problem(oracle, nx, ny, dt, dx=1.0, dy=1.0, limiter="minmod", theta=1.0, time_order=2,
-                   velocity="law", v0=-1.0, v0_field=None, V=(0.0, 0.0), **_):
+                   velocity="law", v0=-1.0, v0_field=None, V=(0.0, 0.0), scheme="semidiscrete", **_):
     v = v0 if v0_field is None else np.asarray(v0_field, dtype=np.float64)
     return oracle.Problem(nx, ny, dx=dx, dy=dy, limiter=limiter, theta=theta, vkind=velocity,
                           v0=float(np.float32(v)) if np.ndim(v) == 0 else v,
-                          V=tuple(float(np.float32(x)) for x in V), time_order=time_order, dt=dt)
+                          V=tuple(float(np.float32(x)) for x in V), time_order=time_order, dt=dt,
+                          scheme=scheme)
 
 
 def rel_l1(g11, g12, o11, o12, ref11, ref12):

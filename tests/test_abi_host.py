@@ -42,6 +42,33 @@ def test_header_enums_match_binding(fdm):
         assert vals["FDM_LIMITER_" + name.upper()] == v
     assert vals["FDM_VELOCITY_LAW"] == fdm.VELOCITIES["law"]
     assert vals["FDM_VELOCITY_PRESCRIBED"] == fdm.VELOCITIES["prescribed"]
+    for name, v in fdm.SCHEMES.items():
+        assert vals["FDM_SCHEME_" + name.upper()] == v
+
+
+def test_struct_offsets_match_the_header(fdm, tmp_path):
+    """Every field offset of the binding's structs equals the C compiler's."""
+    import ctypes
+    import subprocess
+    structs = [fdm.fdm_transport_desc, fdm.fdm_stats, fdm.fdm_loading, fdm.fdm_options,
+               fdm.fdm_tune_trial, fdm.fdm_static_desc]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fdm.h"', "int main(void) {"]
+    expect = []
+    for st in structs:
+        name = st.__name__
+        lines.append('printf("%%zu\\n", sizeof(%s));' % name)
+        expect.append(ctypes.sizeof(st))
+        for f in st._fields_:
+            cname = f[0].rstrip("_")          # Python keywords carry a trailing underscore
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (name, cname))
+            expect.append(getattr(st, f[0]).offset)
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect
 
 
 def test_struct_sizes_match_c_layout(fdm):
@@ -79,6 +106,9 @@ BAD = [
     (dict(velocity=5), "velocity"),
     (dict(v0=float("inf")), "v0"),
     (dict(velocity="prescribed", V=(float("nan"), 0.0)), "V"),
+    (dict(scheme=5), "scheme"),
+    (dict(scheme="fully_discrete", time_order=2), "one pass per step"),
+    (dict(scheme="fully_discrete", time_order=3), "one pass per step"),
 ]
 
 
@@ -90,6 +120,14 @@ def test_invalid_descriptor_rejected_on_host(fdm, kw, msg):
         fdm.fdm_transport_init(fdm.desc(**args))
     assert e.value.status == fdm.FDM_ERR_INVALID_ARG
     assert msg in fdm.fdm_last_error(None)
+
+
+def test_mixed_schemes_rejected(fdm):
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init([fdm.desc(8, 8, time_order=1),
+                                fdm.desc(8, 8, time_order=1, scheme="fully_discrete")])
+    assert e.value.status == fdm.FDM_ERR_INVALID_ARG
+    assert "scheme" in fdm.fdm_last_error(None)
 
 
 def test_mixed_time_orders_rejected(fdm):
