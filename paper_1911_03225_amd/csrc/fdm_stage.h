@@ -204,23 +204,22 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
         return madd(V2, py, V1 * px);
     } else {
         // H = v0 |p| at the four corners (s,t) in {-,+}^2, dH/dp = v0 p/|p|.
-        // |p|^2 carries a bias of the smallest normal number, folded into the
-        // fused squares (px^2 + FLT_MIN, then + py^2), so the reciprocal
-        // square root never sees zero or a subnormal (v_rsq reads those as
-        // zero): the speed at p = 0 is 0, gradients below 1e-19 move with
-        // speed v0 p / 1e-19 instead of a full-speed direction, and
-        // H = v0 sqrt(|p|^2 + 2^-126) differs from v0 |p| by at most
-        // |v0| 2^-63 (H(0) = v0 2^-63; a uniform field of it cancels in every
-        // flux difference, so zero densities under a uniform celerity stay
-        // exactly zero).
+        // |p|^2 is clamped below at the smallest normal number before the
+        // reciprocal square root (v_rsq reads a subnormal as zero): p = 0
+        // still gives H = 0 and speed 0, and gradients below 1e-19 (float)
+        // move with speed v0 p / 1e-19 instead of a full-speed direction.
+        // (Folding the bound into the squares as fma(p, p, FLT_MIN) would
+        // save the four clamps but make H(0) = v0 2^-63: under a celerity
+        // field that seeds 1e-19 densities in empty regions, whose speeds
+        // are then O(v0) -- measurably worse parity.)
         constexpr R kTiny = Arith<R>::tiny;
-        const R xm2 = madd(pxm, pxm, kTiny), xp2 = madd(pxp, pxp, kTiny);
+        const R xm2 = pxm * pxm, xp2 = pxp * pxp;
         const R r00 = madd(pym, pym, xm2), r01 = madd(pyp, pyp, xm2);
         const R r10 = madd(pym, pym, xp2), r11 = madd(pyp, pyp, xp2);
-        const R g00 = v0 * Arith<R>::rsq(r00);
-        const R g01 = v0 * Arith<R>::rsq(r01);
-        const R g10 = v0 * Arith<R>::rsq(r10);
-        const R g11 = v0 * Arith<R>::rsq(r11);
+        const R g00 = v0 * Arith<R>::rsq(vmax(r00, kTiny));
+        const R g01 = v0 * Arith<R>::rsq(vmax(r01, kTiny));
+        const R g10 = v0 * Arith<R>::rsq(vmax(r10, kTiny));
+        const R g11 = v0 * Arith<R>::rsq(vmax(r11, kTiny));
         const R H00 = r00 * g00, H01 = r01 * g01, H10 = r10 * g10, H11 = r11 * g11;
         const R hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
         const R hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
@@ -349,11 +348,11 @@ __device__ __forceinline__ float fd_hamiltonian(float pxm, float pxp, float pym,
         bm = vmin(V2, -Arith<float>::tiny);
     } else {
         constexpr float kTiny = Arith<float>::tiny;
-        const float xm2 = madd(pxm, pxm, kTiny), xp2 = madd(pxp, pxp, kTiny);
-        const float g00 = v0 * Arith<float>::rsq(madd(pym, pym, xm2));
-        const float g01 = v0 * Arith<float>::rsq(madd(pyp, pyp, xm2));
-        const float g10 = v0 * Arith<float>::rsq(madd(pym, pym, xp2));
-        const float g11 = v0 * Arith<float>::rsq(madd(pyp, pyp, xp2));
+        const float xm2 = pxm * pxm, xp2 = pxp * pxp;
+        const float g00 = v0 * Arith<float>::rsq(vmax(madd(pym, pym, xm2), kTiny));
+        const float g01 = v0 * Arith<float>::rsq(vmax(madd(pyp, pyp, xm2), kTiny));
+        const float g10 = v0 * Arith<float>::rsq(vmax(madd(pym, pym, xp2), kTiny));
+        const float g11 = v0 * Arith<float>::rsq(vmax(madd(pyp, pyp, xp2), kTiny));
         const float hx00 = pxm * g00, hx01 = pxm * g01, hx10 = pxp * g10, hx11 = pxp * g11;
         const float hy00 = pym * g00, hy01 = pyp * g01, hy10 = pym * g10, hy11 = pyp * g11;
         ap = vmax(vmax(vmax(vmax(hx00, hx01), hx10), hx11), kTiny);
