@@ -475,11 +475,11 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
                                               &w.d_cd->phi_mean, c->stream, err)
                    : fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, &w.d_cd->sigma_bar, c->stream, err);
         if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
-        ss = fdm::velocity_law(w.tau, w.phi, f64, w.v0, n, law, c->stream, err);
+        ss = fdm::velocity_law(w.tau, w.phi, f64, w.v0, n, law, c->d_absmax, c->stream, err);
         if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
-        // 3. adaptive step, on the device
-        FDM_HIP(c, fdm::launch_absmax(w.v0, n, c->d_absmax, c->stream));
-        FDM_HIP(c, fdm::launch_coupled_dt(c->d_absmax, w.d_cd, d.cfl * h, L.dt_max, d.dx, d.dy, c->stream));
+        // 3. adaptive step from the velocity law's max |v0| partials, on the device
+        FDM_HIP(c, fdm::launch_coupled_dt(c->d_absmax, fdm::velocity_law_blocks(n), w.d_cd, d.cfl * h, L.dt_max,
+                                          d.dx, d.dy, c->stream));
         // 4. one transport step with v0 frozen, per-tile sums of Hhat
         I.hsum = w.d_hsum;
         FDM_HIP(c, fdm::launch_stage(I, mid ? fdm::MODE_MID1 : fdm::MODE_FWD, c->precision, c->stream));
@@ -584,7 +584,8 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     INIT_HIP(hipMalloc((void **)&c->d_partials, sizeof(fdm::StatsPartial) * fdm::kStatsBlocks));
     INIT_HIP(hipMalloc((void **)&c->d_stats, sizeof(double) * 5 * n_instances));
     INIT_HIP(hipHostMalloc((void **)&c->h_stats, sizeof(double) * 5 * n_instances, hipHostMallocDefault));
-    INIT_HIP(hipMalloc((void **)&c->d_absmax, sizeof(float) * fdm::kAbsmaxBlocks));
+    // max |v0| partials: of the celerity field at init, of the velocity law in coupled runs
+    INIT_HIP(hipMalloc((void **)&c->d_absmax, sizeof(float) * std::max(fdm::kAbsmaxBlocks, fdm::kLawBlocks)));
 
     std::vector<float> absmax(fdm::kAbsmaxBlocks);
     int64_t off = 0;

@@ -46,6 +46,41 @@ struct StepCoef {
     int32_t nonfinite, pad;  // a non-finite celerity was seen
 };
 
+// The step of a coupled run from the block partials of max |v0| (a NaN
+// partial marks a non-finite celerity): the largest float not above
+// min(cfl_h / max|v0|, dt_max) (dt_max when nothing moves) and the stage
+// coefficients.  Evaluated by one whole wave.
+__device__ __forceinline__ StepCoef step_coef_from_partials(const float *partial, int np, double cfl_h,
+                                                            double dt_max, double dx, double dy)
+{
+    const int lane = threadIdx.x & 63;
+    float m = 0.0f;
+    int bad = 0;
+    for (int i = lane; i < np; i += 64) {
+        const float x = partial[i];
+        bad |= __builtin_isnan(x) ? 1 : 0;
+        m = fmaxf(m, x);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmaxf(m, __shfl_xor(m, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    const double bound = m > 0.0f ? fmin(cfl_h / (double)m, dt_max) : dt_max;
+    float f = (float)bound;
+    if ((double)f > bound) f = nextafterf(f, 0.0f);
+    StepCoef c;
+    c.dtd = (double)f;
+    c.cxd = (double)f / dx;
+    c.cyd = (double)f / dy;
+    c.cx = (float)c.cxd;
+    c.cy = (float)c.cyd;
+    c.dt = f;
+    c.vmax = m;
+    c.nonfinite = bad;
+    c.pad = 0;
+    return c;
+}
+
 // Scalars of a coupled run, advanced on the device step by step.
 struct CoupledDev {
     StepCoef coef;
@@ -90,11 +125,11 @@ hipError_t launch_copy(void *dst, const void *src, int64_t n, int precision, hip
 
 constexpr int kAbsmaxBlocks = 256;
 
-// Coupled runs: step size from the max |v0| partials (largest float not
-// above min(cfl_h / max|v0|, dt_max)); then, after the stages, the mean slip,
-// mean strain, time and mean stress from the per-tile sums of Hhat.
-hipError_t launch_coupled_dt(const float *absmax_partials, CoupledDev *cd, double cfl_h, double dt_max, double dx,
-                             double dy, hipStream_t s);
+// Coupled runs: the step from the velocity law's max |v0| partials (one
+// wave), and, after the stages, the mean slip, mean strain, time and mean
+// stress from the per-tile sums of Hhat (one block).
+hipError_t launch_coupled_dt(const float *law_partials, int np, CoupledDev *cd, double cfl_h, double dt_max,
+                             double dx, double dy, hipStream_t s);
 hipError_t launch_coupled_slip(const double *hsum, int64_t tiles, int time_order, CoupledDev *cd, double rate,
                                double mu, double frac, double n_nodes, hipStream_t s);
 

@@ -168,34 +168,8 @@ __global__ __launch_bounds__(256) void copy_kernel(S *__restrict__ dst, const S 
 __global__ __launch_bounds__(64) void coupled_dt_kernel(const float *__restrict__ partial, int np, CoupledDev *cd,
                                                         double cfl_h, double dt_max, double dx, double dy)
 {
-    const int lane = threadIdx.x;
-    float m = 0.0f;
-    int bad = 0;
-    for (int i = lane; i < np; i += 64) {
-        const float x = partial[i];
-        bad |= isnan(x) ? 1 : 0;
-        m = fmaxf(m, x);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        m = fmaxf(m, __shfl_xor(m, o, 64));
-        bad |= __shfl_xor(bad, o, 64);
-    }
-    if (lane == 0) {
-        const double bound = m > 0.0f ? fmin(cfl_h / (double)m, dt_max) : dt_max;
-        float f = (float)bound;
-        if ((double)f > bound) f = nextafterf(f, 0.0f);   // the largest float not above the bound
-        StepCoef c;
-        c.dtd = (double)f;
-        c.cxd = (double)f / dx;
-        c.cyd = (double)f / dy;
-        c.cx = (float)c.cxd;
-        c.cy = (float)c.cyd;
-        c.dt = f;
-        c.vmax = m;
-        c.nonfinite = bad;
-        c.pad = 0;
-        cd->coef = c;
-    }
+    const StepCoef c = step_coef_from_partials(partial, np, cfl_h, dt_max, dx, dy);
+    if (threadIdx.x == 0) cd->coef = c;
 }
 
 // Fixed-order compensated sum of v[0..n) by one block of 256 threads.
@@ -243,11 +217,10 @@ __global__ __launch_bounds__(256) void coupled_slip_kernel(const double *__restr
 
 }  // namespace
 
-hipError_t launch_coupled_dt(const float *absmax_partials, CoupledDev *cd, double cfl_h, double dt_max, double dx,
-                             double dy, hipStream_t s)
+hipError_t launch_coupled_dt(const float *law_partials, int np, CoupledDev *cd, double cfl_h, double dt_max,
+                             double dx, double dy, hipStream_t s)
 {
-    hipLaunchKernelGGL(coupled_dt_kernel, dim3(1), dim3(64), 0, s, absmax_partials, kAbsmaxBlocks, cd, cfl_h, dt_max,
-                       dx, dy);
+    hipLaunchKernelGGL(coupled_dt_kernel, dim3(1), dim3(64), 0, s, law_partials, np, cd, cfl_h, dt_max, dx, dy);
     return hipGetLastError();
 }
 

@@ -511,8 +511,33 @@ template <int P> struct Phase {
 // sits in a ring slot fixed by the row number, so no copies rotate it.
 constexpr int kAhead = 2;
 
+// The first midpoint stage runs the MODE_FWD kernel with half the step:
+// halving is exact in float and double, so the coefficients are those of
+// dt/2.
+// Coupled runs: the step is chosen on the device, so the coefficients come
+// from device memory (one scalar load each, once per wave).
+__device__ __forceinline__ void load_coef(InstDev &I)
+{
+    if (I.coef == nullptr) return;
+    I.dtd = I.coef->dtd;
+    I.cxd = I.coef->cxd;
+    I.cyd = I.coef->cyd;
+    I.cx = I.coef->cx;
+    I.cy = I.coef->cy;
+}
+
+__device__ __forceinline__ void halve_step(InstDev &I)
+{
+    I.cx *= 0.5f;
+    I.cy *= 0.5f;
+    I.cxd *= 0.5;
+    I.cyd *= 0.5;
+    I.dtd *= 0.5;
+}
+
+
 template <typename R, typename S, int LK, int VK, bool FIELD, int MODE, bool HSUM = false>
-__device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk, int lane)
+__device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int lane, int half)
 {
     constexpr bool kF64 = sizeof(R) == 8;
     constexpr bool kFD = (VK & VK_FD) != 0;   // fully discrete scheme
@@ -524,8 +549,6 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
     const void *d12 = MODE == MODE_FWD ? I.w12 : I.a12;
     const void *d11 = MODE == MODE_FWD ? I.w11 : I.a11;
     const R theta = kF64 ? R(I.thetad) : R(I.theta);
-    const R cx = kF64 ? R(I.cxd) : R(I.cx);
-    const R cy = kF64 ? R(I.cyd) : R(I.cy);
     const R V1 = R(I.V1), V2 = R(I.V2);
 
     const int gcol = strip * kStrip - kHalo + lane;
@@ -582,6 +605,13 @@ __device__ __forceinline__ void run_tile(const InstDev &I, int strip, int chunk,
         kf = kf1;
     }
     int kf1 = next_row(kf, ny);
+
+    // The step coefficients, with the first loads already in flight (coupled
+    // runs read them from device memory).
+    load_coef(I);
+    if (half) halve_step(I);
+    const R cx = kF64 ? R(I.cxd) : R(I.cx);
+    const R cy = kF64 ? R(I.cyd) : R(I.cy);
 
     auto body = [&](int it, auto phase) {
         constexpr int p = decltype(phase)::value;
@@ -703,39 +733,13 @@ __device__ __forceinline__ int64_t xcd_tile(int blocks_per_xcd)
     return logical * kWavesPerBlock + wave;
 }
 
-// The first midpoint stage runs the MODE_FWD kernel with half the step:
-// halving is exact in float and double, so the coefficients are those of
-// dt/2.
-// Coupled runs: the step is chosen on the device, so the coefficients come
-// from device memory (one scalar load each, once per wave).
-__device__ __forceinline__ void load_coef(InstDev &I)
-{
-    if (I.coef == nullptr) return;
-    I.dtd = I.coef->dtd;
-    I.cxd = I.coef->cxd;
-    I.cyd = I.coef->cyd;
-    I.cx = I.coef->cx;
-    I.cy = I.coef->cy;
-}
-
-__device__ __forceinline__ void halve_step(InstDev &I)
-{
-    I.cx *= 0.5f;
-    I.cy *= 0.5f;
-    I.cxd *= 0.5;
-    I.cyd *= 0.5;
-    I.dtd *= 0.5;
-}
-
 template <typename R, typename S, int LK, int VK, bool FIELD, int MODE, bool HSUM = false>
 __global__ __launch_bounds__(kBlock) void stage_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd, int half)
 {
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
-    load_coef(I);
-    if (half) halve_step(I);
     const int t = (int)tile;
-    run_tile<R, S, LK, VK, FIELD, MODE, HSUM>(I, t % I.strips, t / I.strips, threadIdx.x & 63);
+    run_tile<R, S, LK, VK, FIELD, MODE, HSUM>(I, t % I.strips, t / I.strips, threadIdx.x & 63, half);
 }
 
 // Batched: one launch for every tile of every instance; tile_inst maps a
@@ -748,44 +752,42 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__
 {
     const int64_t tile = xcd_tile(blocks_per_xcd);
     if (tile >= total_tiles) return;
-    InstDev I = insts[tile_inst[tile]];
-    load_coef(I);
-    if (half) halve_step(I);
+    const InstDev I = insts[tile_inst[tile]];
     const int local = (int)(tile - I.tile_begin);
     const int strip = local % I.strips, chunk = local / I.strips;
     const int lane = threadIdx.x & 63;
     const int lk = limiter_kind(I.limiter);
     if constexpr (FD) {
         if (I.vkind == VK_PRESCRIBED_FD) {
-            if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane);
-            else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane);
-            else run_tile<R, S, LK_THETA, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane);
+            if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane, half);
+            else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane, half);
+            else run_tile<R, S, LK_THETA, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane, half);
             return;
         }
         if (I.vkind == VK_LAW_FD) {
             if (I.v0f != nullptr) {
-                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane);
-                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane);
-                else run_tile<R, S, LK_THETA, VK_LAW_FD, true, MODE>(I, strip, chunk, lane);
+                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane, half);
+                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane, half);
+                else run_tile<R, S, LK_THETA, VK_LAW_FD, true, MODE>(I, strip, chunk, lane, half);
             } else {
-                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane);
-                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane);
-                else run_tile<R, S, LK_THETA, VK_LAW_FD, false, MODE>(I, strip, chunk, lane);
+                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane, half);
+                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane, half);
+                else run_tile<R, S, LK_THETA, VK_LAW_FD, false, MODE>(I, strip, chunk, lane, half);
             }
         }
         return;
     } else if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
-        else run_tile<R, S, LK_THETA, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane);
+        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane, half);
+        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane, half);
+        else run_tile<R, S, LK_THETA, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane, half);
     } else if (I.v0f != nullptr) {
-        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW, true, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW, true, MODE>(I, strip, chunk, lane);
-        else run_tile<R, S, LK_THETA, VK_LAW, true, MODE>(I, strip, chunk, lane);
+        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW, true, MODE>(I, strip, chunk, lane, half);
+        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW, true, MODE>(I, strip, chunk, lane, half);
+        else run_tile<R, S, LK_THETA, VK_LAW, true, MODE>(I, strip, chunk, lane, half);
     } else {
-        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW, false, MODE>(I, strip, chunk, lane);
-        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW, false, MODE>(I, strip, chunk, lane);
-        else run_tile<R, S, LK_THETA, VK_LAW, false, MODE>(I, strip, chunk, lane);
+        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW, false, MODE>(I, strip, chunk, lane, half);
+        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW, false, MODE>(I, strip, chunk, lane, half);
+        else run_tile<R, S, LK_THETA, VK_LAW, false, MODE>(I, strip, chunk, lane, half);
     }
 }
 

@@ -48,7 +48,11 @@ struct LawParams {
     double tau0, mobility, tau_y, beta;
     const float *mfield;
 };
+// Also writes one max |v0| partial per block (NaN marks a non-finite value)
+// into partial[0 .. velocity_law_blocks(n)), for the step size.
+constexpr int kLawBlocks = 1024;
+int velocity_law_blocks(int64_t n);
 StaticStatus velocity_law(const void *tau13, const void *phi, bool f64, float *v0, int64_t n, const LawParams &law,
-                          hipStream_t s, std::string &err);
+                          float *partial, hipStream_t s, std::string &err);
 
 }  // namespace fdm

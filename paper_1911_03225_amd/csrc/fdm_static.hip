@@ -106,8 +106,12 @@ __global__ __launch_bounds__(256) void pack_kernel(T *dst, const T *a11, const T
 //   wiggly:    v0 = m (tau_y cos(phi / beta) - tau13).
 template <typename T, bool WIGGLY>
 __global__ __launch_bounds__(256) void velocity_law_kernel(const T *tau, const T *phi, const float *mfield, float *v0,
-                                                            int64_t n, T tau0, T mobility, T tau_y, T beta)
+                                                            int64_t n, T tau0, T mobility, T tau_y, T beta,
+                                                            float *partial)
 {
+    __shared__ float lds[4];
+    float amax = 0.0f;   // this thread's max |v0|, NaN once a non-finite value is seen
+    bool bad = false;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const T t = tau[i];
@@ -120,7 +124,23 @@ __global__ __launch_bounds__(256) void velocity_law_kernel(const T *tau, const T
             const T s = a > T(0) ? copysign(a, t) : T(0);
             v = -(m * s);
         }
-        v0[i] = (float)v;
+        const float vf = (float)v;
+        v0[i] = vf;
+        bad |= !isfinite(vf);
+        amax = fmaxf(amax, fabsf(vf));
+    }
+    // block partial of max |v0| for the step size (NaN marks a non-finite value)
+    if (bad) amax = __builtin_nanf("");
+    for (int o = 32; o > 0; o >>= 1) {
+        const float other = __shfl_xor(amax, o, 64);
+        amax = (isnan(amax) || isnan(other)) ? __builtin_nanf("") : fmaxf(amax, other);
+    }
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float r = lds[0];
+        for (int w = 1; w < 4; ++w) r = (isnan(r) || isnan(lds[w])) ? __builtin_nanf("") : fmaxf(r, lds[w]);
+        partial[blockIdx.x] = r;
     }
 }
 
@@ -399,26 +419,28 @@ StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau
 }
 }  // namespace
 
+int velocity_law_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, kLawBlocks); }
+
 StaticStatus velocity_law(const void *tau13, const void *phi, bool f64, float *v0, int64_t n, const LawParams &L,
-                          hipStream_t s, std::string &err)
+                          float *partial, hipStream_t s, std::string &err)
 {
-    const unsigned b = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    const unsigned b = (unsigned)velocity_law_blocks(n);
     if (f64) {
         if (L.wiggly)
             hipLaunchKernelGGL((velocity_law_kernel<double, true>), dim3(b), dim3(256), 0, s, (const double *)tau13,
-                               (const double *)phi, L.mfield, v0, n, L.tau0, L.mobility, L.tau_y, L.beta);
+                               (const double *)phi, L.mfield, v0, n, L.tau0, L.mobility, L.tau_y, L.beta, partial);
         else
             hipLaunchKernelGGL((velocity_law_kernel<double, false>), dim3(b), dim3(256), 0, s, (const double *)tau13,
-                               (const double *)phi, L.mfield, v0, n, L.tau0, L.mobility, L.tau_y, L.beta);
+                               (const double *)phi, L.mfield, v0, n, L.tau0, L.mobility, L.tau_y, L.beta, partial);
     } else {
         if (L.wiggly)
             hipLaunchKernelGGL((velocity_law_kernel<float, true>), dim3(b), dim3(256), 0, s, (const float *)tau13,
                                (const float *)phi, L.mfield, v0, n, (float)L.tau0, (float)L.mobility,
-                               (float)L.tau_y, (float)L.beta);
+                               (float)L.tau_y, (float)L.beta, partial);
         else
             hipLaunchKernelGGL((velocity_law_kernel<float, false>), dim3(b), dim3(256), 0, s, (const float *)tau13,
                                (const float *)phi, L.mfield, v0, n, (float)L.tau0, (float)L.mobility,
-                               (float)L.tau_y, (float)L.beta);
+                               (float)L.tau_y, (float)L.beta, partial);
     }
     ST_HIP(hipGetLastError());
     return StaticStatus::Ok;
