@@ -250,7 +250,66 @@ def coupled_leg(fdm, workloads, n_steps, log, n=512):
             "stress_strain_columns": ["eps13", "sigma13", "phi_mean", "vmax"]}
 
 
-def fully_discrete_leg(fdm, workloads, n, K, limiter, log):
+def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
+    """The spatially varying celerity workload: 4096^2 diagonal bands (64
+    bands, seed 3) under a Fourier-mode celerity field, minmod, Heun, CFL
+    0.45.  State, stage buffer and field (320 MiB) exceed the 256 MB MALL, so
+    this is the HBM-side figure; a device-to-device copy of the same bytes
+    per step is timed beside it as the practical streaming peak."""
+    import torch
+    a11, a12, v0 = workloads.c3_bands(n, seed=3)
+    dev = torch.device("cuda:0")
+    t11, t12 = torch.from_numpy(a11).to(dev), torch.from_numpy(a12).to(dev)
+    tv = torch.from_numpy(v0).to(dev)
+    stream = torch.cuda.current_stream()
+    ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter="minmod", cfl=0.45, v0_field=tv), stream=stream,
+                                 keep=[tv])
+    if autotune:
+        fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=5)
+    rows = fdm.fdm_tile_rows(ctx, 0)
+    fdm.fdm_run(ctx, t11, t12, K, K)          # captures the chunk graph
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fdm.fdm_run(ctx, t11, t12, K, K)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1000.0)
+    fdm.fdm_destroy(ctx)
+    t = sorted(times)[1]
+    value = n * n * K / t
+    # reference: copy the bytes one step must move at least (unfused stages:
+    # 48 B per node with the field) with a plain device-to-device copy
+    nbytes = 48 * n * n
+    src = torch.empty(nbytes // 8, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) / 1000.0) / 1e9
+    del src, dst
+    alg = value * 20 / 1e9     # algorithmic bytes per cell-update with a field: 20
+    unfused = value * 48 / 1e9
+    log("bench[c3]: %dx%d %.3e cell-updates/s (%d-row tiles), copy reference %.0f GB/s" %
+        (n, n, value, rows, copy_gbs))
+    return {"grid": [n, n], "limiter": "minmod", "cfl": 0.45, "steps": K, "tile_rows": rows,
+            "ms_per_step": round(1e3 * t / K, 4), "cell_updates_per_s": round(value, 1),
+            "hbm_frac_algorithmic": round(alg / HBM_PEAK_GBS, 4),
+            "unfused_stream_gbs": round(unfused, 1),
+            "copy_reference_gbs": round(copy_gbs, 1),
+            "unfused_stream_frac_of_copy": round(unfused / copy_gbs, 4),
+            "timing": "HIP events around graph-replayed chunks, median of 3; copy: torch device copy of the same "
+                      "48 B/node footprint"}
+
+
+def fully_discrete_leg(fdm, workloads, n, K, limiter, log, autotune=True):
     """The same single-loop workload advanced by the paper's one-pass fully
     discrete scheme (one stage launch per step) at CFL 0.25."""
     import torch
@@ -260,7 +319,8 @@ def fully_discrete_leg(fdm, workloads, n, K, limiter, log):
     stream = torch.cuda.current_stream()
     ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter=limiter, cfl=0.25, v0=-1.0, time_order=1,
                                           scheme="fully_discrete"), stream=stream)
-    fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=10)
+    if autotune:
+        fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=10)
     rows = fdm.fdm_tile_rows(ctx, 0)
     fdm.fdm_run(ctx, t11, t12, K, K)          # captures the chunk graph
     torch.cuda.synchronize()
@@ -298,6 +358,7 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=500)
     ap.add_argument("--no-c4", action="store_true", help="skip the coupled-run measurement")
     ap.add_argument("--no-fd", action="store_true", help="skip the fully-discrete-scheme measurement")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 4096^2 celerity-field measurement")
     ap.add_argument("--c4-steps", type=int, default=5000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="N",
                     help="also run one single-stage (Euler) step on an N x N zero state: its copy-back is a "
@@ -410,9 +471,13 @@ def main():
     if not args.no_c4:
         c4 = coupled_leg(fdm, workloads, args.c4_steps, log)
 
+    c3 = None
+    if not args.no_c3:
+        c3 = c3_leg(fdm, workloads, 100, log, autotune=not args.no_autotune)
+
     fd = None
     if not args.no_fd:
-        fd = fully_discrete_leg(fdm, workloads, n, K, args.limiter, log)
+        fd = fully_discrete_leg(fdm, workloads, n, K, args.limiter, log, autotune=not args.no_autotune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -450,6 +515,7 @@ def main():
         "batched_vs_plain": c5,
         "coupled": c4,
         "fully_discrete": fd,
+        "celerity_field_4096": c3,
         "final_stats": {"step": final["step"], "sum_abs": final["sum_abs"], "max_norm": final["max_norm"],
                         "drift11": final["drift11"], "drift12": final["drift12"]},
     }
