@@ -41,7 +41,8 @@ OPS_PER_NODE_STAGE = 120
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_c2_2048_fp32_traffic.json")
 KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_kernels.hip"]
 STAGE_NAMES = {"fwd": "stage_kernel<float, float, 2, 0, false, 0, false>",
-               "heun2": "stage_kernel<float, float, 2, 0, false, 2, false>"}
+               "heun2": "stage_kernel<float, float, 2, 0, false, 2, false>",
+               "fused": "fused_kernel<2, 0, false>"}
 COPY_NAME = "copy_kernel<float>"
 
 
@@ -58,13 +59,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def _counter_means(directory, counter):
-    """Mean counter value (KiB per dispatch) per kernel family in a rocprofv3 CSV directory."""
+def _counter_means(directories, counter):
+    """Mean counter value (KiB per dispatch) per kernel family over rocprofv3
+    CSV directories (comma-separated); families absent from them are left out."""
     import csv
     import glob
-    files = glob.glob(os.path.join(directory, "*counter_collection.csv"))
+    files = [f for d in directories.split(",") for f in glob.glob(os.path.join(d, "*counter_collection.csv"))]
     if not files:
-        raise SystemExit("no counter_collection.csv under %s" % directory)
+        raise SystemExit("no counter_collection.csv under %s" % directories)
     import collections
     # (family, grid size) -> values; the copy probe's own stage launch has the
     # same kernel name on a larger grid, so each family keeps its most
@@ -85,16 +87,19 @@ def _counter_means(directory, counter):
     for k in list(STAGE_NAMES) + ["copy"]:
         groups = [(len(v), g, v) for (fam, g), v in vals.items() if fam == k]
         if not groups:
-            raise SystemExit("no %s samples for %s in %s" % (counter, k, directory))
+            if k == "copy":
+                raise SystemExit("no %s samples for the copy probe in %s" % (counter, directories))
+            continue
         _, grid[k], v = max(groups)
         out[k] = sum(v) / len(v)
     return out, grid
 
 
-def rows_from_grid(grid_threads, n):
+def rows_from_grid(grid_threads, n, strip=60):
     """Tile height of a stage launch on an n x n grid from its thread count:
-    blocks of 4 waves, rounded up to a multiple of 8 blocks (one per XCD)."""
-    strips = -(-n // 60)
+    blocks of 4 waves, rounded up to a multiple of 8 blocks (one per XCD);
+    strip: output columns per wave (56 for the fused kernel)."""
+    strips = -(-n // strip)
     for r in range(1, n + 1):
         tiles = strips * -(-n // r)
         blocks = -(-tiles // 4)
@@ -110,26 +115,33 @@ def write_traffic_summary(fetch_dir, write_dir, out, copy_n, grid_n):
     counter reports for it is that counter's calibration factor."""
     fetch, grid = _counter_means(fetch_dir, "FETCH_SIZE")
     write, _ = _counter_means(write_dir, "WRITE_SIZE")
-    rows = rows_from_grid(grid["fwd"], grid_n)
     copy_kib = 4.0 * copy_n * copy_n / 1024.0
     ff, wf = copy_kib / fetch["copy"], copy_kib / write["copy"]
     per = {k: {"fetch_kib": round(fetch[k], 1), "write_kib": round(write[k], 1),
-               "bytes": round((fetch[k] * ff + write[k] * wf) * 1024.0)} for k in STAGE_NAMES}
-    summary = {"kernel_source_sha256": kernel_source_hash(), "grid": grid_n, "tile_rows": rows,
+               "bytes": round((fetch[k] * ff + write[k] * wf) * 1024.0),
+               "tile_rows": rows_from_grid(grid[k], grid_n, 56 if k == "fused" else 60)}
+           for k in STAGE_NAMES if k in fetch and k in write}
+    unfused = [per[k]["bytes"] for k in ("fwd", "heun2") if k in per]
+    summary = {"kernel_source_sha256": kernel_source_hash(), "grid": grid_n,
+               "tile_rows": per["fwd"]["tile_rows"] if "fwd" in per else None,
                "copy_probe_n": copy_n,
                "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
                "copy_fetch_kib": round(fetch["copy"], 1), "copy_write_kib": round(write["copy"], 1),
                "stage": per,
-               "bytes_per_launch": round(sum(v["bytes"] for v in per.values()) / len(per))}
+               "bytes_per_launch": round(sum(unfused) / len(unfused)) if len(unfused) == 2 else None,
+               "fused_bytes_per_launch": per["fused"]["bytes"] if "fused" in per else None}
     with open(out, "w") as fh:
         json.dump(summary, fh, indent=1)
     print(json.dumps(summary))
 
 
-def load_traffic(grid_n, precision, limiter, tile_rows):
-    """Bytes per stage launch for this workload, or None when no summary was
-    measured on the current kernel sources and configuration (tile_rows: the
-    height the timed launches used)."""
+def load_traffic(grid_n, precision, limiter, tile_rows, fused=False):
+    """(bytes per launch, tile height the counters were taken at) for this
+    workload, or None when no summary was measured on the current kernel
+    sources and configuration.  Unfused: the average of the two stage
+    launches, at the same tile height as the timed launches.  Fused: the
+    one launch per step; the autotuner's height may differ from the
+    profiled one (reported beside it)."""
     if precision != "fp32" or limiter != "superbee" or not os.path.exists(TRAFFIC_FILE):
         return None
     try:
@@ -137,10 +149,14 @@ def load_traffic(grid_n, precision, limiter, tile_rows):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("grid") != grid_n \
-            or t.get("tile_rows") != tile_rows:
+    if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("grid") != grid_n:
         return None
-    return t
+    if fused:
+        f = t.get("stage", {}).get("fused")
+        return (f["bytes"], f["tile_rows"]) if f else None
+    if t.get("tile_rows") != tile_rows or not t.get("bytes_per_launch"):
+        return None
+    return t["bytes_per_launch"], t["tile_rows"]
 
 
 def _make_instance(inst):
@@ -264,8 +280,10 @@ def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
     stream = torch.cuda.current_stream()
     ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter="minmod", cfl=0.45, v0_field=tv), stream=stream,
                                  keep=[tv])
+    sched = "plain"
     if autotune:
-        fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=5)
+        trials = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=5)
+        sched = min(trials, key=lambda t: t["seconds_per_step"])["schedule"]
     rows = fdm.fdm_tile_rows(ctx, 0)
     fdm.fdm_run(ctx, t11, t12, K, K)          # captures the chunk graph
     torch.cuda.synchronize()
@@ -297,9 +315,9 @@ def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
     del src, dst
     alg = value * 20 / 1e9     # algorithmic bytes per cell-update with a field: 20
     unfused = value * 48 / 1e9
-    log("bench[c3]: %dx%d %.3e cell-updates/s (%d-row tiles), copy reference %.0f GB/s" %
-        (n, n, value, rows, copy_gbs))
-    return {"grid": [n, n], "limiter": "minmod", "cfl": 0.45, "steps": K, "tile_rows": rows,
+    log("bench[c3]: %dx%d %.3e cell-updates/s (%d-row tiles, %s), copy reference %.0f GB/s" %
+        (n, n, value, rows, sched, copy_gbs))
+    return {"grid": [n, n], "limiter": "minmod", "cfl": 0.45, "steps": K, "tile_rows": rows, "schedule": sched,
             "ms_per_step": round(1e3 * t / K, 4), "cell_updates_per_s": round(value, 1),
             "hbm_frac_algorithmic": round(alg / HBM_PEAK_GBS, 4),
             "unfused_stream_gbs": round(unfused, 1),
@@ -359,6 +377,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the coupled-run measurement")
     ap.add_argument("--no-fd", action="store_true", help="skip the fully-discrete-scheme measurement")
     ap.add_argument("--no-c3", action="store_true", help="skip the 4096^2 celerity-field measurement")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "plain", "fused"],
+                    help="launch schedule of the main workload (auto: the autotuner may pick fused)")
     ap.add_argument("--c4-steps", type=int, default=5000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="N",
                     help="also run one single-stage (Euler) step on an N x N zero state: its copy-back is a "
@@ -394,7 +414,7 @@ def main():
     t11 = torch.from_numpy(a11).to(dev).to(state)
     t12 = torch.from_numpy(a12).to(dev).to(state)
     stream = torch.cuda.current_stream()
-    options = {"tile_rows": args.tile_rows, "precision": args.precision}
+    options = {"tile_rows": args.tile_rows, "precision": args.precision, "schedule": args.schedule}
     ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter=args.limiter, cfl=cfl, v0=-1.0), options=options,
                                  stream=stream)
     dt = fdm.fdm_transport_dt(ctx)
@@ -404,8 +424,14 @@ def main():
         log("bench: autotune: %s" % ", ".join("%d rows %.2f us" % (t["tile_rows"], 1e6 * t["seconds_per_step"])
                                                for t in tuning))
     rows_used = fdm.fdm_tile_rows(ctx, 0)
+    if tuning:
+        sched_used = min(tuning, key=lambda t: t["seconds_per_step"])["schedule"]
+    else:
+        sched_used = "fused" if args.schedule == "fused" else "plain"
+    fused = sched_used == "fused"
 
-    log("bench: warmup %d steps + one captured chunk of %d (%d-row tiles)" % (W, K, rows_used))
+    log("bench: warmup %d steps + one captured chunk of %d (%d-row tiles, %s launches)"
+        % (W, K, rows_used, sched_used))
     fdm.fdm_transport_step(ctx, t11, t12, W)
     fdm.fdm_run(ctx, t11, t12, K, K)          # captures the chunk graph
     torch.cuda.synchronize()
@@ -426,28 +452,30 @@ def main():
     value = cells * K / t_med
     ms_per_step = 1e3 * t_med / K
     # Two stage launches per step (first and second Heun stage, the same
-    # kernel template); the per-chunk diagnostics are < 1% of the region.
-    # Dominant kernel: the stage kernel, ALU-bound.
-    launches = 2 * K
+    # kernel template), or one fused launch; the per-chunk diagnostics are
+    # < 1% of the region.  Dominant kernel: the stage kernel, ALU-bound.
+    stages_per_launch = 2 if fused else 1
+    launches = K * 2 // stages_per_launch
     kernel_s = t_med / launches
-    ops_per_launch = OPS_PER_NODE_STAGE * cells
+    ops_per_launch = OPS_PER_NODE_STAGE * cells * stages_per_launch
     achieved = ops_per_launch / kernel_s / 1e12
-    tr = load_traffic(n, args.precision, args.limiter, rows_used)
+    tr = load_traffic(n, args.precision, args.limiter, rows_used, fused)
+    alg_bytes = BYTES_PER_CELL_STEP * cells * stages_per_launch // 2
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                "traffic": tr["bytes_per_launch"] if tr else None,
-                "traffic_vs_algorithmic": round(tr["bytes_per_launch"] / (BYTES_PER_CELL_STEP / 2 * cells), 3)
-                if tr else None,
-                "kernel": "stage_kernel (first and second Heun stage)",
+                "traffic": tr[0] if tr else None,
+                "traffic_tile_rows": tr[1] if tr else None,
+                "traffic_vs_algorithmic": round(tr[0] / alg_bytes, 3) if tr else None,
+                "kernel": "fused_kernel (both Heun stages)" if fused
+                else "stage_kernel (first and second Heun stage)",
                 "kernel_avg_us": round(1e6 * kernel_s, 2), "ops_per_launch": ops_per_launch,
-                "hbm_bytes_per_launch": BYTES_PER_CELL_STEP // 2 * cells,
-                "unfused_min_bytes_per_launch": 20 * cells,
-                "hbm_achieved_gbs": round(BYTES_PER_CELL_STEP / 2 * cells / kernel_s / 1e9, 1),
+                "hbm_bytes_per_launch": alg_bytes,
+                "unfused_min_bytes_per_launch": 20 * cells * stages_per_launch,
+                "hbm_achieved_gbs": round(alg_bytes / kernel_s / 1e9, 1),
                 # measured L2-to-fabric bytes (counter passes) over this run's launch time;
                 # at 2048^2 the working set sits in the 256 MB MALL, which serves much of it
-                "fabric_achieved_gbs": round(tr["bytes_per_launch"] / kernel_s / 1e9, 1) if tr else None,
-                "fabric_frac_of_hbm_peak": round(tr["bytes_per_launch"] / kernel_s / 1e9 / HBM_PEAK_GBS, 4)
-                if tr else None}
+                "fabric_achieved_gbs": round(tr[0] / kernel_s / 1e9, 1) if tr else None,
+                "fabric_frac_of_hbm_peak": round(tr[0] / kernel_s / 1e9 / HBM_PEAK_GBS, 4) if tr else None}
     final = hist[-1][0]
     fdm.fdm_destroy(ctx)
 
@@ -506,7 +534,7 @@ def main():
         "config": {"workload": "single loop %dx%d (ring R=%g sigma=%g), LAW v0=-1, %s, Heun, CFL %g"
                                % (n, n, R, sigma, args.limiter, cfl),
                    "grid": [n, n], "limiter": args.limiter, "cfl": cfl, "dt": dt, "time_order": 2,
-                   "chunk_steps": K, "tile_rows": rows_used,
+                   "chunk_steps": K, "tile_rows": rows_used, "schedule": sched_used,
                    "tiling": "autotuned" if tuning else ("fixed" if args.tile_rows else "default rule"),
                    "precision": args.precision},
         "hbm_frac_algorithmic": round(value * BYTES_PER_CELL_STEP / 1e9 / HBM_PEAK_GBS, 4),

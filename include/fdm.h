@@ -124,7 +124,19 @@ typedef struct fdm_transport_desc {
 typedef enum fdm_schedule {
     FDM_SCHEDULE_AUTO = 0,     /* batched launches when n_instances > 1        */
     FDM_SCHEDULE_BATCHED = 1,  /* one launch per stage for all instances       */
-    FDM_SCHEDULE_PLAIN = 2     /* one launch per stage per instance            */
+    FDM_SCHEDULE_PLAIN = 2,    /* one launch per stage per instance            */
+    FDM_SCHEDULE_FUSED = 3     /* one launch per step per instance: both Heun
+                                  stages in one pass, the first stage's
+                                  densities kept in registers, so a step reads
+                                  and writes the state once (8 B per node each
+                                  way, + 4 B read with a celerity field, against
+                                  20 + 28 B unfused).  FP32 precision,
+                                  time_order 2, semi-discrete scheme only.  The
+                                  same results bit for bit; faster where the
+                                  state exceeds the on-chip cache and the
+                                  unfused launches stream from HBM, slower
+                                  where it fits (about 15-25% more arithmetic:
+                                  halo columns and rows of the first stage)   */
 } fdm_schedule;
 
 /* Precision of the stage kernels.
@@ -309,7 +321,7 @@ int32_t fdm_tile_rows(const fdm_ctx *ctx, int32_t instance);
 /* One timed candidate of fdm_autotune. */
 typedef struct fdm_tune_trial {
     int32_t tile_rows;       /* rows per wave tile tried (all instances)        */
-    int32_t schedule;        /* FDM_SCHEDULE_BATCHED or FDM_SCHEDULE_PLAIN      */
+    int32_t schedule;        /* FDM_SCHEDULE_BATCHED, _PLAIN or _FUSED          */
     double seconds_per_step; /* faster of two timed runs of trial_steps steps   */
 } fdm_tune_trial;
 
@@ -317,8 +329,9 @@ typedef struct fdm_tune_trial {
  * changes no result bit, only speed).  Copies the given state into scratch
  * memory, and on that copy times trial_steps (>= 1) steps for each candidate
  * tile height in {4, 8, 12, 16, 24, 32, 48, 64} (heights above the tallest
- * instance are skipped) and, for a context of several instances created with
- * FDM_SCHEDULE_AUTO, for both the batched and the plain schedule.  The
+ * instance are skipped) and, for a context created with FDM_SCHEDULE_AUTO,
+ * for each schedule that applies: batched and plain (several instances),
+ * and fused (FP32 precision, time_order 2, semi-discrete scheme).  The
  * context then keeps the fastest candidate.  alpha11/alpha12 are read, never
  * written; the step count and diagnostics baseline are unchanged.  Up to
  * max_trials measured candidates are written to trials (may be NULL when

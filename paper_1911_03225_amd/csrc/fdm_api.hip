@@ -30,6 +30,7 @@ struct fdm_ctx {
     int32_t schedule = FDM_SCHEDULE_AUTO;
     int32_t precision = FDM_PRECISION_FP32;
     bool batched = false;
+    bool fused = false;                     // fused two-stage Heun launches
     std::vector<fdm_transport_desc> desc;
     std::vector<InstDev> inst;              // host copies of the device views
     std::vector<float> dt;                  // float32 step per instance
@@ -251,7 +252,11 @@ fdm_status bind(fdm_ctx *c, void *const *a11, void *const *a12)
 // Enqueue n_steps on stream s for the bound arrays.
 fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
 {
-    for (int32_t step = 0; step < n_steps; ++step) {
+    if (c->fused) {   // both Heun stages per launch, ping-pong between the state and the stage buffer
+        for (int32_t step = 0; step < n_steps; ++step)
+            for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_fused(c->inst[i], step & 1, s));
+    }
+    for (int32_t step = 0; step < (c->fused ? 0 : n_steps); ++step) {
         int modes[2];
         int nm;
         if (c->time_order == 2) {
@@ -275,9 +280,9 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
             }
         }
     }
-    // Euler ping-pongs between the state and the stage buffer; after an odd
-    // count the newest state sits in the stage buffer.
-    if (c->time_order == 1 && (n_steps & 1)) {
+    // Euler and the fused Heun step ping-pong between the state and the stage
+    // buffer; after an odd count the newest state sits in the stage buffer.
+    if ((c->time_order == 1 || c->fused) && (n_steps & 1)) {
         for (int i = 0; i < c->n; ++i) {
             const int64_t n = (int64_t)c->inst[i].nx * c->inst[i].ny;
             FDM_HIP(c, fdm::launch_copy(c->inst[i].a11, c->inst[i].w11, n, c->precision, s));
@@ -526,7 +531,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     if (!descs || n_instances < 1) return fail(nullptr, FDM_ERR_INVALID_ARG, "need at least one descriptor");
     fdm_options opt = {0, 0, 0, 0};
     if (options) opt = *options;
-    if (opt.schedule < FDM_SCHEDULE_AUTO || opt.schedule > FDM_SCHEDULE_PLAIN)
+    if (opt.schedule < FDM_SCHEDULE_AUTO || opt.schedule > FDM_SCHEDULE_FUSED)
         return fail(nullptr, FDM_ERR_INVALID_ARG, "unknown schedule");
     if (opt.tile_rows < 0) return fail(nullptr, FDM_ERR_INVALID_ARG, "tile_rows must be >= 0");
     if (opt.fused != 0) return fail(nullptr, FDM_ERR_INVALID_ARG, "fused is reserved and must be 0");
@@ -544,6 +549,10 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
             return fail(nullptr, FDM_ERR_INVALID_ARG, "all instances of a context must share the scheme");
         order = o;
     }
+    if (opt.schedule == FDM_SCHEDULE_FUSED &&
+        !(opt.precision == FDM_PRECISION_FP32 && order == 2 && descs[0].scheme == FDM_SCHEME_SEMIDISCRETE))
+        return fail(nullptr, FDM_ERR_INVALID_ARG,
+                    "the fused schedule needs FP32 precision, time_order 2 and the semi-discrete scheme");
     // Courant bound of a fixed dt needs s_max; uniform cases are checked here,
     // field cases after the device reduction below.
     fdm_ctx *c = new (std::nothrow) fdm_ctx;
@@ -554,7 +563,8 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     c->fd = descs[0].scheme == FDM_SCHEME_FULLY_DISCRETE;
     c->schedule = opt.schedule;
     c->precision = opt.precision;
-    c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN;
+    c->fused = opt.schedule == FDM_SCHEDULE_FUSED;
+    c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN && !c->fused;
     c->desc.assign(descs, descs + n_instances);
     c->inst.resize(n_instances);
     c->dt.resize(n_instances);
@@ -813,16 +823,23 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
     }
     std::vector<void *> s11(c->n), s12(c->n);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool was_batched = c->batched;
+    const bool was_batched = c->batched, was_fused = c->fused;
     int best_rows = -1;
-    bool best_batched = was_batched;
+    bool best_batched = was_batched, best_fused = was_fused;
     double best = 0.0;
     int32_t count = 0;
     int max_ny = 0;
     for (int i = 0; i < c->n; ++i) max_ny = std::max(max_ny, c->desc[i].ny);
-    std::vector<bool> schedules;
-    if (c->n > 1 && c->schedule == FDM_SCHEDULE_AUTO) schedules = {true, false};
-    else schedules = {was_batched};
+    // candidate schedules: the requested one, or under AUTO batched and plain
+    // (several instances) and the fused Heun launches where they apply
+    std::vector<int> schedules;
+    if (c->schedule == FDM_SCHEDULE_AUTO) {
+        if (c->n > 1) schedules = {FDM_SCHEDULE_BATCHED, FDM_SCHEDULE_PLAIN};
+        else schedules = {FDM_SCHEDULE_PLAIN};
+        if (c->precision == fdm::PREC_FP32 && c->time_order == 2 && !c->fd) schedules.push_back(FDM_SCHEDULE_FUSED);
+    } else {
+        schedules = {was_fused ? FDM_SCHEDULE_FUSED : was_batched ? FDM_SCHEDULE_BATCHED : FDM_SCHEDULE_PLAIN};
+    }
 
     auto run = [&]() -> fdm_status {
         int64_t off = 0;
@@ -836,10 +853,12 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
         }
         FDM_HIP(c, hipEventCreate(&e0));
         FDM_HIP(c, hipEventCreate(&e1));
-        for (bool batched : schedules) {
+        for (int sched : schedules) {
+            const bool batched = sched == FDM_SCHEDULE_BATCHED, fused = sched == FDM_SCHEDULE_FUSED;
             for (int rows : {4, 8, 12, 16, 24, 32, 48, 64}) {
                 if (rows > max_ny && rows != 4) continue;
                 c->batched = batched;
+                c->fused = fused;
                 fdm_status r = retile(c, rows);
                 if (r != FDM_OK) return r;
                 r = bind(c, s11.data(), s12.data());
@@ -860,7 +879,7 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
                 const double sec = std::min(t[0], t[1]);
                 if (count < max_trials) {
                     trials[count].tile_rows = rows;
-                    trials[count].schedule = batched ? FDM_SCHEDULE_BATCHED : FDM_SCHEDULE_PLAIN;
+                    trials[count].schedule = sched;
                     trials[count].seconds_per_step = sec;
                 }
                 ++count;
@@ -868,6 +887,7 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
                     best = sec;
                     best_rows = rows;
                     best_batched = batched;
+                    best_fused = fused;
                 }
             }
         }
@@ -880,11 +900,13 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
     (void)hipFree(scratch);
     if (st == FDM_OK && best_rows > 0) {
         c->batched = best_batched;
+        c->fused = best_fused;
         st = retile(c, best_rows);
         if (st == FDM_OK) c->requested_rows = best_rows;
     } else if (!c->sticky) {
         // restore the previous tiling after a non-device failure
         c->batched = was_batched;
+        c->fused = was_fused;
         (void)retile(c, c->requested_rows);
     }
     c->table_valid = false;   // the table points at the scratch arrays

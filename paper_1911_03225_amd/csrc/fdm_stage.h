@@ -719,6 +719,173 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
     }
 }
 
+// ------------------------------------------------------------ fused Heun
+//
+// Both Heun stages in one pass (float only, semi-discrete scheme): each wave
+// runs the first stage two node rows ahead of the second and keeps the
+// first stage's densities in registers, so a step reads the state (and the
+// celerity field) once and writes the new state once -- 8 B per node in and
+// out instead of 20 and 28 for the two unfused launches.  The second stage
+// needs first-stage values two lanes and two rows beyond its outputs, so a
+// wave owns 56 output columns (4 halo lanes on each side) and the first
+// stage runs four rows beyond the tile.  Every value is computed with the
+// same operations as in the unfused kernels (same node function, same
+// updates), so the result is the same bit for bit.  Reads src, writes dst
+// (distinct buffers: neighbouring tiles still read src).
+constexpr int kFStrip = 56, kFHalo = 4;
+
+template <int LK, int VK, bool FIELD>
+__device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int chunk, int lane, const void *src11,
+                                               const void *src12, void *dst11, void *dst12)
+{
+    using R = float;
+    using S = float;
+    const int nx = I.nx, ny = I.ny;
+    const R theta = I.theta, cx = I.cx, cy = I.cy;
+    const R V1 = I.V1, V2 = I.V2;
+
+    const int gcol = strip * kFStrip - kFHalo + lane;
+    int col = gcol % nx;
+    if (col < 0) col += nx;
+    const uint32_t off = (uint32_t)col * 4u;
+    const bool out_col = lane >= kFHalo && lane < kFHalo + kFStrip && gcol < nx;
+    const int k0 = chunk * I.rows;
+    const int nrows = min(I.rows, ny - k0);
+    const uint32_t off_st = out_col ? off : kSkip;
+
+    // Iteration i (0 .. nrows + 4): the first stage ("A") at node row
+    // m = k0 - 2 + i, then, from i = 4 on, the second stage ("B") at node
+    // row k = m - 2.  Ring slots, with p = i & 7: input alpha_11 of row
+    // mA0 + j in y[j & 7] (A reads rows m-1 .. m+1, B the base row m-3, loads
+    // run to m+3), input alpha_12 and v0 of row mA0 + j in slot j & 7 (A row
+    // m, B base row m-2, loads to m+2); A's outputs alpha_12 of row m in
+    // wxo[p & 3] and alpha_11 of row m-1 in wyo[(p + 3) & 3].
+    S y[8], wx_[8], wxo[4], wyo[4];
+    float v0_[8];
+    R slA[2], hhA[2], slB[2], hhB[2];
+    for (int j = 0; j < 8; ++j) v0_[j] = 0.0f;
+    for (int j = 0; j < 4; ++j) wxo[j] = wyo[j] = S(0);
+    slB[0] = slB[1] = hhB[0] = hhB[1] = R(0);
+    float ydmB = 0.0f, ydmsB = 0.0f;
+
+    int k = (k0 - 4) % ny;   // A starts at node row mA0 = k0 - 2
+    if (k < 0) k += ny;
+    const R ym2 = R(at(row_ptr<S>(src11, k, nx), off));
+    k = next_row(k, ny);
+    y[7] = at(row_ptr<S>(src11, k, nx), off);
+    int kA = next_row(k, ny);                  // A's node row
+    y[0] = at(row_ptr<S>(src11, kA, nx), off);
+    slA[1] = limited_slope<LK>(ym2, R(y[7]), R(y[0]), theta);
+    hhA[1] = R(0);
+    float ydmA = float(R(y[0]) - R(y[7]));
+    float ydmsA = LK == LK_SUPERBEE ? 2.0f * ydmA : float(theta) * ydmA;
+
+    const int last = nrows + 4;   // the last iteration
+    int kf = kA;
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+        const int kf1 = next_row(kf, ny);
+        wx_[j] = at(row_ptr<S>(src12, kf, nx), off);
+        y[j + 1] = at(row_ptr<S>(src11, kf1, nx), off);
+        if constexpr (FIELD) v0_[j] = at(row_ptr<float>(I.v0f, kf, nx), off);
+        kf = kf1;
+    }
+    int kf1 = next_row(kf, ny);
+    int kB = k0, kBprev = k0 == 0 ? ny - 1 : k0 - 1;   // B's node row and the row above it
+
+    // The node function of both stages: Steps 1-4 at one node from the
+    // alpha_11 rows above/at/below and alpha_12 of the row, with the y slope
+    // carried from the previous row (as in run_tile).
+    auto node = [&](R ym1, R y0, R yp1, R wx, R v0, R *sl, int h, int hp, float &ydm, float &ydms) {
+        const R s0 = y_slope_carried<LK>(ym1, y0, yp1, theta, ydm, ydms);
+        const R pyp = -madd(R(-0.5), s0, y0);
+        const R pym = -madd(R(0.5), sl[hp], ym1);
+        sl[h] = s0;
+        const R wl = from_left(wx), wr = from_right(wx);
+        const R sx = limited_slope<LK>(wl, wx, wr, theta);
+        const R pxp = madd(R(-0.5), sx, wx);
+        const R pxm = from_left(madd(R(0.5), sx, wx));
+        return numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
+    };
+
+    auto body = [&](int it, auto phase) {
+        constexpr int p = decltype(phase)::value;
+        constexpr int h = p & 1, hp = h ^ 1;
+        // ---- stage A at node row kA
+        {
+            const R ym1 = R(y[(p + 7) & 7]), y0 = R(y[p]), yp1 = R(y[(p + 1) & 7]);
+            const R wx = R(wx_[p]);
+            const R v0 = FIELD ? R(v0_[p]) : R(I.v0);
+            {   // operands of A's row m + kAhead (none past the last iteration)
+                const bool live = it + kAhead <= last;
+                wx_[(p + kAhead) & 7] = at(row_ptr<S>(src12, kf, nx, live), off);
+                y[(p + kAhead + 1) & 7] = at(row_ptr<S>(src11, kf1, nx, live), off);
+                if constexpr (FIELD) v0_[(p + kAhead) & 7] = at(row_ptr<float>(I.v0f, kf, nx, live), off);
+                kf = kf1;
+                kf1 = next_row(kf1, ny);
+            }
+            const R hv = node(ym1, y0, yp1, wx, v0, slA, h, hp, ydmA, ydmsA);
+            const R hr = from_right(hv);
+            const R hprev = hhA[hp];
+            hhA[h] = hv;
+            wxo[p & 3] = S(madd(-cx, hr - hv, wx));          // alpha_12 of row m after stage 1
+            wyo[(p + 3) & 3] = S(madd(cy, hv - hprev, ym1));  // alpha_11 of row m-1 after stage 1
+            kA = next_row(kA, ny);
+        }
+        if (it < 4) return;
+        // ---- stage B at node row kB = m - 2
+        if (it == 4) {   // slope at edge k0-1/2 from stage-1 rows k0-2 .. k0
+            const R a = R(wyo[p & 3]), b = R(wyo[(p + 1) & 3]), c = R(wyo[(p + 2) & 3]);
+            slB[hp] = limited_slope<LK>(a, b, c, theta);
+            ydmB = float(c - b);
+            ydmsB = LK == LK_SUPERBEE ? 2.0f * ydmB : float(theta) * ydmB;
+            hhB[hp] = R(0);
+        }
+        {
+            const int bi = it - 4;
+            const R ym1 = R(wyo[(p + 1) & 3]), y0 = R(wyo[(p + 2) & 3]), yp1 = R(wyo[(p + 3) & 3]);
+            const R wx = R(wxo[(p + 2) & 3]);
+            const R v0 = FIELD ? R(v0_[(p + 6) & 7]) : R(I.v0);
+            const R b12 = R(wx_[(p + 6) & 7]), b11 = R(y[(p + 5) & 7]);   // the step's initial state
+            const R hv = node(ym1, y0, yp1, wx, v0, slB, h, hp, ydmB, ydmsB);
+            const R hr = from_right(hv);
+            const R hprev = hhB[hp];
+            hhB[h] = hv;
+            {
+                R nv = madd(-cx, hr - hv, wx);
+                nv = madd(R(0.5), b12, R(0.5) * nv);
+                put(row_ptr<S>(dst12, kB, nx, bi < nrows), off_st, S(nv));
+            }
+            {
+                R nv = madd(cy, hv - hprev, ym1);
+                nv = madd(R(0.5), b11, R(0.5) * nv);
+                put(row_ptr<S>(dst11, kBprev, nx, bi > 0), off_st, S(nv));
+            }
+            kBprev = kB;
+            kB = next_row(kB, ny);
+        }
+    };
+
+    for (int it = 0;; it += 8) {
+        body(it, Phase<0>{});
+        if (it + 1 > last) break;
+        body(it + 1, Phase<1>{});
+        if (it + 2 > last) break;
+        body(it + 2, Phase<2>{});
+        if (it + 3 > last) break;
+        body(it + 3, Phase<3>{});
+        if (it + 4 > last) break;
+        body(it + 4, Phase<4>{});
+        if (it + 5 > last) break;
+        body(it + 5, Phase<5>{});
+        if (it + 6 > last) break;
+        body(it + 6, Phase<6>{});
+        if (it + 7 > last) break;
+        body(it + 7, Phase<7>{});
+        if (it + 8 > last) break;
+    }
+}
+
 // Tiles are numbered row band first (tile = chunk * strips + strip), so
 // consecutive waves -- the four of a block, and neighbouring blocks -- are
 // side-by-side strips walking the same rows at the same time: the 128-byte
@@ -821,6 +988,32 @@ hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
             hipLaunchKernelGGL((stage_kernel<R, S, LK, VK, FIELD, MODE_HEUN2, HSUM>), grid, block, 0, s, I, tiles,
                                per_xcd, 0);
     }
+    return hipGetLastError();
+}
+
+// Fused Heun step: dir 0 reads the state and writes the stage buffer, dir 1
+// the other way round.
+template <int LK, int VK, bool FIELD>
+__global__ __launch_bounds__(kBlock) void fused_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd,
+                                                       int strips, int dir)
+{
+    const int64_t tile = xcd_tile(blocks_per_xcd);
+    if (tile >= total_tiles) return;
+    const int t = (int)tile;
+    const void *s11 = dir ? I.w11 : I.a11, *s12 = dir ? I.w12 : I.a12;
+    void *d11 = dir ? I.a11 : I.w11, *d12 = dir ? I.a12 : I.w12;
+    run_tile_fused<LK, VK, FIELD>(I, t % strips, t / strips, threadIdx.x & 63, s11, s12, d11, d12);
+}
+
+template <int LK, int VK, bool FIELD>
+hipError_t launch_fused_t(const InstDev &I, int dir, hipStream_t s)
+{
+    const int strips = (I.nx + kFStrip - 1) / kFStrip;
+    const int64_t tiles = (int64_t)strips * ((I.ny + I.rows - 1) / I.rows);
+    const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per_xcd = (int)((blocks + 7) / 8);
+    hipLaunchKernelGGL((fused_kernel<LK, VK, FIELD>), dim3(8 * per_xcd), dim3(kBlock), 0, s, I, tiles, per_xcd,
+                       strips, dir);
     return hipGetLastError();
 }
 

@@ -15,6 +15,29 @@ hipError_t launch_stage_f32(const InstDev &I, int mode, hipStream_t s)
     return launch_stage_r<float, float>(I, mode, s);
 }
 
+namespace {
+hipError_t launch_fused_r(const InstDev &I, int dir, hipStream_t s)
+{
+    const int lk = limiter_kind(I.limiter);
+    if (I.vkind == VK_PRESCRIBED) {
+        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_PRESCRIBED, false>(I, dir, s);
+        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_PRESCRIBED, false>(I, dir, s);
+        return launch_fused_t<LK_THETA, VK_PRESCRIBED, false>(I, dir, s);
+    }
+    if (I.vkind != VK_LAW) return hipErrorInvalidValue;   // semi-discrete scheme only
+    if (I.v0f != nullptr) {
+        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, true>(I, dir, s);
+        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, true>(I, dir, s);
+        return launch_fused_t<LK_THETA, VK_LAW, true>(I, dir, s);
+    }
+    if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, false>(I, dir, s);
+    if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, false>(I, dir, s);
+    return launch_fused_t<LK_THETA, VK_LAW, false>(I, dir, s);
+}
+}  // namespace
+
+hipError_t launch_fused(const InstDev &I, int dir, hipStream_t s) { return launch_fused_r(I, dir, s); }
+
 hipError_t launch_stage_batched_f32(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
                                     int mode, bool fd, hipStream_t s)
 {

@@ -22,7 +22,7 @@ FDM_OK, FDM_ERR_INVALID_ARG, FDM_ERR_DEVICE, FDM_ERR_OUT_OF_MEMORY = 0, 1, 2, 3
 FDM_ERR_CFL, FDM_ERR_NONFINITE, FDM_ERR_UNSUPPORTED = 4, 5, 6
 LIMITERS = {"none": 0, "minmod": 1, "mc": 2, "theta": 3, "superbee": 4}
 VELOCITIES = {"law": 0, "prescribed": 1}
-SCHEDULES = {"auto": 0, "batched": 1, "plain": 2}
+SCHEDULES = {"auto": 0, "batched": 1, "plain": 2, "fused": 3}
 PRECISIONS = {"fp32": 0, "fp64_arith": 1, "fp64": 2}
 SCHEMES = {"semidiscrete": 0, "fully_discrete": 1}
 

@@ -44,6 +44,8 @@ def test_header_enums_match_binding(fdm):
     assert vals["FDM_VELOCITY_PRESCRIBED"] == fdm.VELOCITIES["prescribed"]
     for name, v in fdm.SCHEMES.items():
         assert vals["FDM_SCHEME_" + name.upper()] == v
+    for name, v in fdm.SCHEDULES.items():
+        assert vals["FDM_SCHEDULE_" + name.upper()] == v
 
 
 def test_struct_offsets_match_the_header(fdm, tmp_path):
@@ -204,3 +206,17 @@ def test_invalid_options_rejected(fdm):
         with pytest.raises(fdm.FdmError) as e:
             fdm.fdm_transport_init(fdm.desc(16, 16), options=opts)
         assert e.value.status == fdm.FDM_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw,opts", [
+    (dict(), {"schedule": "fused", "precision": "fp64"}),
+    (dict(), {"schedule": "fused", "precision": "fp64_arith"}),
+    (dict(time_order=1), {"schedule": "fused"}),
+    (dict(time_order=3), {"schedule": "fused"}),
+    (dict(time_order=1, scheme="fully_discrete"), {"schedule": "fused"}),
+])
+def test_fused_schedule_needs_fp32_heun_semidiscrete(fdm, kw, opts):
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init(fdm.desc(16, 16, **kw), options=opts)
+    assert e.value.status == fdm.FDM_ERR_INVALID_ARG
+    assert "fused" in fdm.fdm_last_error(None)

@@ -1,0 +1,151 @@
+"""The fused Heun schedule (both stages in one launch per step, first-stage
+densities kept in registers) against the unfused launches and the oracle.
+
+The fused kernel evaluates every node with the same operations as the two
+unfused stage kernels, so results must agree bit for bit, whatever the grid
+size, tile height, step count (odd counts end in the stage buffer and are
+copied back) and schedule path (direct steps or graph-replayed chunks).
+"""
+import numpy as np
+import pytest
+
+from gpu_util import compare_run, gpu_run, to_dev, tolerance
+from paper_1911_03225_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FUSED = {"schedule": "fused"}
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_03225_amd import fdm as F
+    F.load_library()
+    return F
+
+
+def _same(a, b):
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+CASES = [
+    dict(limiter="superbee", v0=-1.0),
+    dict(limiter="mc", v0=0.8),
+    dict(limiter="minmod", v0=-0.6),
+    dict(limiter="theta", theta=1.4, v0=-1.0),
+    dict(limiter="none", v0=-1.0),
+    dict(limiter="mc", velocity="prescribed", V=(0.7, -0.4)),
+]
+
+
+@pytest.mark.parametrize("kw", CASES)
+@pytest.mark.parametrize("steps", [1, 6, 7])
+def test_fused_equals_unfused_bitwise(fdm, kw, steps):
+    a11, a12 = W.ring(150, 130, R=35.0, sigma=3.0)
+    _, f = gpu_run(a11, a12, steps, options=FUSED, cfl=0.4, **dict(kw))
+    _, u = gpu_run(a11, a12, steps, options={"schedule": "plain"}, cfl=0.4, **dict(kw))
+    _same(f[-1], u[-1])
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (3, 5), (55, 9), (56, 2), (57, 3), (113, 67), (200, 1), (1, 40)])
+def test_fused_odd_sizes_bitwise(fdm, nx, ny):
+    rng = np.random.default_rng(nx * 1000 + ny)
+    phi = rng.normal(size=(ny, nx))
+    phi = phi + np.roll(phi, 1, 0) + np.roll(phi, 1, 1)
+    a12 = (np.roll(phi, -1, 1) - phi + 0.3).astype(np.float32)
+    a11 = (-(np.roll(phi, -1, 0) - phi) - 0.2).astype(np.float32)
+    kw = dict(limiter="superbee", cfl=0.4, v0=-0.8)
+    _, f = gpu_run(a11, a12, 5, options=FUSED, **kw)
+    _, u = gpu_run(a11, a12, 5, options={"schedule": "plain"}, **kw)
+    _same(f[-1], u[-1])
+
+
+@pytest.mark.parametrize("rows", [1, 3, 12, 64])
+def test_fused_tile_heights_bitwise(fdm, rows):
+    a11, a12 = W.ring(190, 170, R=45.0, sigma=4.0)
+    kw = dict(limiter="superbee", cfl=0.4, v0=-1.0)
+    _, f = gpu_run(a11, a12, 9, options={"schedule": "fused", "tile_rows": rows}, **kw)
+    _, u = gpu_run(a11, a12, 9, options={"schedule": "plain"}, **kw)
+    _same(f[-1], u[-1])
+
+
+def test_fused_celerity_field_bitwise_and_oracle(fdm, oracle):
+    nx, ny = 192, 128
+    v0 = W.fourier_celerity(nx, ny, np.random.default_rng(3))
+    a11, a12 = W.diagonal_bands(nx, ny, np.random.default_rng(4), n_bands=12)
+    _, f = gpu_run(a11, a12, 40, options=FUSED, limiter="minmod", cfl=0.4, v0_field=v0)
+    _, u = gpu_run(a11, a12, 40, options={"schedule": "plain"}, limiter="minmod", cfl=0.4, v0_field=v0)
+    _same(f[-1], u[-1])
+    dt, rep, g, o = compare_run(oracle, a11, a12, 200, every=100, options=FUSED, limiter="minmod", cfl=0.45,
+                                v0_field=v0)
+    for s, e1, einf in rep:
+        assert e1 <= tolerance(s), (s, e1, einf)
+
+
+def test_fused_ring_oracle_parity(fdm, oracle):
+    a11, a12 = W.ring(256, 256, R=60.0, sigma=6.0)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 500, every=100, options=FUSED, limiter="superbee", cfl=0.4,
+                                v0=-1.0)
+    for s, e1, einf in rep:
+        assert e1 <= tolerance(s), (s, e1, einf)
+
+
+@pytest.mark.parametrize("chunk", [5, 8])
+def test_fused_graph_chunks_bitwise(fdm, chunk):
+    """fdm_run replays captured chunks (odd chunks end with the copy back)."""
+    import torch
+    a11, a12 = W.ring(160, 120, R=30.0, sigma=3.0)
+    outs = []
+    for opts in (FUSED, {"schedule": "plain"}):
+        t11, t12 = to_dev(a11), to_dev(a12)
+        ctx = fdm.fdm_transport_init(fdm.desc(160, 120, limiter="mc", cfl=0.4, v0=-1.0), options=opts)
+        hist = fdm.fdm_run(ctx, t11, t12, 3 * chunk, chunk)
+        torch.cuda.synchronize()
+        outs.append((t11.cpu().numpy(), t12.cpu().numpy(), [h[0]["sum_abs"] for h in hist]))
+        fdm.fdm_destroy(ctx)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+def test_fused_several_instances_equal_batched(fdm):
+    import torch
+    shapes = [(64, 48), (130, 70), (33, 257)]
+    lims = ["minmod", "superbee", "mc"]
+    states = [W.ring(nx, ny, R=min(nx, ny) / 4, sigma=2.0) for nx, ny in shapes]
+    descs = [fdm.desc(nx, ny, limiter=lim, cfl=0.4, v0=-1.0) for (nx, ny), lim in zip(shapes, lims)]
+    res = {}
+    for sched in ("fused", "batched"):
+        t = [(to_dev(a), to_dev(b)) for a, b in states]
+        ctx = fdm.fdm_transport_init(descs, options={"schedule": sched})
+        fdm.fdm_transport_step(ctx, [x[0] for x in t], [x[1] for x in t], 11)
+        torch.cuda.synchronize()
+        res[sched] = [(x.cpu().numpy(), y.cpu().numpy()) for x, y in t]
+        fdm.fdm_destroy(ctx)
+    for (f11, f12), (b11, b12) in zip(res["fused"], res["batched"]):
+        assert np.array_equal(f11, b11) and np.array_equal(f12, b12)
+
+
+def test_autotune_tries_the_fused_schedule(fdm):
+    """AUTO on an FP32 Heun context also times the fused launches; the tuned
+    context gives the same bits as an untuned one."""
+    import torch
+    a11, a12 = W.ring(256, 256, R=60.0, sigma=4.0)
+    t11, t12 = to_dev(a11), to_dev(a12)
+    ctx = fdm.fdm_transport_init(fdm.desc(256, 256, limiter="superbee", cfl=0.4, v0=-1.0))
+    trials = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=2)
+    assert {t["schedule"] for t in trials} == {"plain", "fused"}
+    fdm.fdm_transport_step(ctx, t11, t12, 7)
+    torch.cuda.synchronize()
+    fdm.fdm_destroy(ctx)
+    _, u = gpu_run(a11, a12, 7, options={"schedule": "plain"}, limiter="superbee", cfl=0.4, v0=-1.0)
+    assert np.array_equal(t11.cpu().numpy(), u[-1][1]) and np.array_equal(t12.cpu().numpy(), u[-1][2])
+    # FP64 contexts do not offer it
+    ctx = fdm.fdm_transport_init(fdm.desc(64, 64, limiter="mc", cfl=0.4, v0=-1.0),
+                                 options={"precision": "fp64_arith"})
+    s11, s12 = to_dev(a11[:64, :64]), to_dev(a12[:64, :64])
+    trials = fdm.fdm_autotune(ctx, [s11], [s12], trial_steps=1)
+    assert {t["schedule"] for t in trials} == {"plain"}
+    fdm.fdm_destroy(ctx)
