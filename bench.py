@@ -166,7 +166,8 @@ def _make_instance(inst):
 
 def batched_vs_plain(fdm, workloads, K, log, autotune=True):
     """The batched workload (384 instances, ~90M nodes): one K-step chunk as
-    one graph of batched launches against one launch per instance per stage."""
+    one graph of batched launches against one launch per instance per stage,
+    and as one graph of batched fused Heun launches (one per step)."""
     import concurrent.futures as cf
     import numpy as np
     import torch
@@ -189,7 +190,7 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
     out = {}
     finals = {}
     rows = {}
-    for sched in ("batched", "plain"):
+    for sched in ("batched", "plain", "fused"):
         s11 = [b.clone() for b in base11]
         s12 = [b.clone() for b in base12]
         ctx = fdm.fdm_transport_init(descs, options={"schedule": sched}, stream=stream, keep=fields)
@@ -198,7 +199,7 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
             log("bench[c5]: %s autotune: %s" % (sched, ", ".join("%d rows %.3f ms" % (
                 t["tile_rows"], 1e3 * t["seconds_per_step"]) for t in trials)))
         rows[sched] = fdm.fdm_tile_rows(ctx, 0)
-        if sched == "batched":
+        if sched != "plain":
             fdm.fdm_run(ctx, s11, s12, K, K, history=False)      # capture + warm
         else:
             fdm.fdm_transport_step(ctx, s11, s12, 2)
@@ -212,7 +213,7 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        if sched == "batched":
+        if sched != "plain":
             fdm.fdm_run(ctx, s11, s12, K, K, history=False)
         else:
             fdm.fdm_transport_step(ctx, s11, s12, K)
@@ -226,12 +227,15 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
                       "nonfinite_instances": sum(1 for st in stats if st["nonfinite"])}
         finals[sched] = (s11, s12)
         log("bench[c5]: %s %d steps in %.3f s (%.3e cell-updates/s)" % (sched, K, dt_s, nodes * K / dt_s))
-    same = all(torch.equal(a, b) for a, b in zip(finals["batched"][0], finals["plain"][0])) and \
-        all(torch.equal(a, b) for a, b in zip(finals["batched"][1], finals["plain"][1]))
+    def same(a, b):
+        return all(torch.equal(x, y) for x, y in zip(finals[a][0], finals[b][0])) and \
+            all(torch.equal(x, y) for x, y in zip(finals[a][1], finals[b][1]))
     return {"instances": len(insts), "nodes": nodes, "chunk_steps": K,
-            "batched": out["batched"], "plain": out["plain"],
+            "batched": out["batched"], "plain": out["plain"], "fused_batched": out["fused"],
             "speedup": round(out["plain"]["seconds"] / out["batched"]["seconds"], 3),
-            "bitwise_equal": bool(same)}
+            "fused_speedup_vs_plain": round(out["plain"]["seconds"] / out["fused"]["seconds"], 3),
+            "bitwise_equal": bool(same("batched", "plain")),
+            "fused_bitwise_equal": bool(same("fused", "plain"))}
 
 
 def coupled_leg(fdm, workloads, n_steps, log, n=512):

@@ -253,8 +253,12 @@ fdm_status bind(fdm_ctx *c, void *const *a11, void *const *a12)
 fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
 {
     if (c->fused) {   // both Heun stages per launch, ping-pong between the state and the stage buffer
-        for (int32_t step = 0; step < n_steps; ++step)
-            for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_fused(c->inst[i], step & 1, s));
+        for (int32_t step = 0; step < n_steps; ++step) {
+            if (c->batched)
+                FDM_HIP(c, fdm::launch_fused_batched(c->d_inst, c->d_tile_inst, c->total_tiles, step & 1, s));
+            else
+                for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_fused(c->inst[i], step & 1, s));
+        }
     }
     for (int32_t step = 0; step < (c->fused ? 0 : n_steps); ++step) {
         int modes[2];
@@ -305,9 +309,10 @@ fdm_status retile(fdm_ctx *c, int requested)
         InstDev &I = c->inst[i];
         I.rows = pick_rows(c->batched ? batch_strip_rows : strip_rows_of(d), d.ny, requested);
         I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
+        I.fstrips = (d.nx + fdm::kFusedStrip - 1) / fdm::kFusedStrip;
         I.chunks = (d.ny + I.rows - 1) / I.rows;
-        I.tile_begin = tile;
-        tile += (int64_t)I.strips * I.chunks;
+        I.tile_begin = tile;   // in the tiling of the schedule's kernel
+        tile += (int64_t)(c->fused ? I.fstrips : I.strips) * I.chunks;
     }
     c->total_tiles = tile;
     c->table_valid = false;
@@ -331,7 +336,8 @@ fdm_status retile(fdm_ctx *c, int requested)
         FDM_HIP(c, hipHostMalloc((void **)&c->h_inst_pinned, sizeof(InstDev) * c->n, hipHostMallocDefault));
     std::vector<int32_t> map(tile);
     for (int i = 0; i < c->n; ++i) {
-        const int64_t b = c->inst[i].tile_begin, e = b + (int64_t)c->inst[i].strips * c->inst[i].chunks;
+        const InstDev &I = c->inst[i];
+        const int64_t b = I.tile_begin, e = b + (int64_t)(c->fused ? I.fstrips : I.strips) * I.chunks;
         for (int64_t t = b; t < e; ++t) map[t] = i;
     }
     FDM_HIP(c, hipMemcpy(c->d_tile_inst, map.data(), sizeof(int32_t) * tile, hipMemcpyHostToDevice));
@@ -564,7 +570,7 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     c->schedule = opt.schedule;
     c->precision = opt.precision;
     c->fused = opt.schedule == FDM_SCHEDULE_FUSED;
-    c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN && !c->fused;
+    c->batched = n_instances > 1 && opt.schedule != FDM_SCHEDULE_PLAIN;   // fused: one launch for all
     c->desc.assign(descs, descs + n_instances);
     c->inst.resize(n_instances);
     c->dt.resize(n_instances);
@@ -854,7 +860,8 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
         FDM_HIP(c, hipEventCreate(&e0));
         FDM_HIP(c, hipEventCreate(&e1));
         for (int sched : schedules) {
-            const bool batched = sched == FDM_SCHEDULE_BATCHED, fused = sched == FDM_SCHEDULE_FUSED;
+            const bool fused = sched == FDM_SCHEDULE_FUSED;
+            const bool batched = sched == FDM_SCHEDULE_BATCHED || (fused && c->n > 1);
             for (int rows : {4, 8, 12, 16, 24, 32, 48, 64}) {
                 if (rows > max_ny && rows != 4) continue;
                 c->batched = batched;

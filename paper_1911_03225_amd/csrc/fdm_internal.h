@@ -13,6 +13,7 @@ namespace fdm {
 constexpr int kWave = 64;
 constexpr int kHalo = 2;
 constexpr int kStrip = kWave - 2 * kHalo;   // 60 output columns per wave
+constexpr int kFusedStrip = kWave - 8;      // 56: the fused Heun kernel's (4 halo lanes a side)
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 
@@ -99,7 +100,7 @@ struct InstDev {
     int32_t limiter, vkind;
     int32_t rows;            // rows per wave tile
     int32_t strips, chunks;  // tiles along x and y
-    int32_t pad;
+    int32_t fstrips;         // tiles along x of the fused Heun kernel (56 columns)
     int64_t tile_begin;      // first global tile of this instance (batched)
     double cxd, cyd, thetad; // the same coefficients for FP64 arithmetic
     double dtd, dxd, dyd;    // step and spacings (FP64 update in definition form)
@@ -123,6 +124,10 @@ hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_
 // semi-discrete scheme): dir 0 from the state into the stage buffer, dir 1
 // back; tiles of I.rows rows and 56 columns.
 hipError_t launch_fused(const InstDev &I, int dir, hipStream_t s);
+// The same for every instance of a batched context in one launch (the tile
+// map and tile_begin of the fused tiling).
+hipError_t launch_fused_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles, int dir,
+                                hipStream_t s);
 hipError_t launch_stats(const void *a11, const void *a12, int64_t n, int precision,
                         StatsPartial *d_partials, double *d_out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t n, int precision, hipStream_t s);

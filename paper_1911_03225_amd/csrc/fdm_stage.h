@@ -732,7 +732,7 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
 // same operations as in the unfused kernels (same node function, same
 // updates), so the result is the same bit for bit.  Reads src, writes dst
 // (distinct buffers: neighbouring tiles still read src).
-constexpr int kFStrip = 56, kFHalo = 4;
+constexpr int kFStrip = kFusedStrip, kFHalo = 4;
 
 template <int LK, int VK, bool FIELD>
 __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int chunk, int lane, const void *src11,
@@ -1003,6 +1003,39 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(InstDev I, int64_t total_
     const void *s11 = dir ? I.w11 : I.a11, *s12 = dir ? I.w12 : I.a12;
     void *d11 = dir ? I.a11 : I.w11, *d12 = dir ? I.a12 : I.w12;
     run_tile_fused<LK, VK, FIELD>(I, t % strips, t / strips, threadIdx.x & 63, s11, s12, d11, d12);
+}
+
+// Batched fused step: one launch for the fused tiles of every instance;
+// limiter, Hamiltonian and field presence are per instance (wave-uniform).
+template <int DIR>
+__global__ __launch_bounds__(kBlock) void fused_kernel_batched(const InstDev *__restrict__ insts,
+                                                               const int32_t *__restrict__ tile_inst,
+                                                               int64_t total_tiles, int blocks_per_xcd)
+{
+    const int64_t tile = xcd_tile(blocks_per_xcd);
+    if (tile >= total_tiles) return;
+    const InstDev I = insts[tile_inst[tile]];
+    const int local = (int)(tile - I.tile_begin);
+    const int strip = local % I.fstrips, chunk = local / I.fstrips;
+    const int lane = threadIdx.x & 63;
+    const void *s11 = DIR ? I.w11 : I.a11, *s12 = DIR ? I.w12 : I.a12;
+    void *d11 = DIR ? I.a11 : I.w11, *d12 = DIR ? I.a12 : I.w12;
+    const int lk = limiter_kind(I.limiter);
+    if (I.vkind == VK_PRESCRIBED) {
+        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_PRESCRIBED, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else if (lk == LK_SUPERBEE)
+            run_tile_fused<LK_SUPERBEE, VK_PRESCRIBED, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else run_tile_fused<LK_THETA, VK_PRESCRIBED, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+    } else if (I.v0f != nullptr) {
+        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, true>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else if (lk == LK_SUPERBEE) run_tile_fused<LK_SUPERBEE, VK_LAW, true>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else run_tile_fused<LK_THETA, VK_LAW, true>(I, strip, chunk, lane, s11, s12, d11, d12);
+    } else {
+        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else if (lk == LK_SUPERBEE)
+            run_tile_fused<LK_SUPERBEE, VK_LAW, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else run_tile_fused<LK_THETA, VK_LAW, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+    }
 }
 
 template <int LK, int VK, bool FIELD>

@@ -38,6 +38,19 @@ hipError_t launch_fused_r(const InstDev &I, int dir, hipStream_t s)
 
 hipError_t launch_fused(const InstDev &I, int dir, hipStream_t s) { return launch_fused_r(I, dir, s); }
 
+hipError_t launch_fused_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles, int dir,
+                                hipStream_t s)
+{
+    const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per_xcd = (int)((blocks + 7) / 8);
+    const dim3 grid(8 * per_xcd), block(kBlock);
+    if (dir)
+        hipLaunchKernelGGL(fused_kernel_batched<1>, grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+    else
+        hipLaunchKernelGGL(fused_kernel_batched<0>, grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+    return hipGetLastError();
+}
+
 hipError_t launch_stage_batched_f32(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles,
                                     int mode, bool fd, hipStream_t s)
 {

@@ -111,21 +111,28 @@ def test_fused_graph_chunks_bitwise(fdm, chunk):
 
 
 def test_fused_several_instances_equal_batched(fdm):
+    """Several instances: one batched fused launch per step for all of them
+    (different sizes, limiters, a celerity field, a prescribed velocity)."""
     import torch
-    shapes = [(64, 48), (130, 70), (33, 257)]
-    lims = ["minmod", "superbee", "mc"]
+    shapes = [(64, 48), (130, 70), (33, 257), (200, 9)]
+    lims = ["minmod", "superbee", "mc", "superbee"]
     states = [W.ring(nx, ny, R=min(nx, ny) / 4, sigma=2.0) for nx, ny in shapes]
-    descs = [fdm.desc(nx, ny, limiter=lim, cfl=0.4, v0=-1.0) for (nx, ny), lim in zip(shapes, lims)]
+    field = to_dev(W.fourier_celerity(130, 70, np.random.default_rng(9)))
+    descs = [fdm.desc(64, 48, limiter="minmod", cfl=0.4, v0=-1.0),
+             fdm.desc(130, 70, limiter="superbee", cfl=0.4, v0_field=field),
+             fdm.desc(33, 257, limiter="mc", cfl=0.4, v0=0.7),
+             fdm.desc(200, 9, limiter="superbee", cfl=0.4, velocity="prescribed", V=(-0.6, 0.8))]
     res = {}
-    for sched in ("fused", "batched"):
+    for sched in ("fused", "batched", "plain"):
         t = [(to_dev(a), to_dev(b)) for a, b in states]
-        ctx = fdm.fdm_transport_init(descs, options={"schedule": sched})
+        ctx = fdm.fdm_transport_init(descs, options={"schedule": sched}, keep=[field])
         fdm.fdm_transport_step(ctx, [x[0] for x in t], [x[1] for x in t], 11)
         torch.cuda.synchronize()
         res[sched] = [(x.cpu().numpy(), y.cpu().numpy()) for x, y in t]
         fdm.fdm_destroy(ctx)
-    for (f11, f12), (b11, b12) in zip(res["fused"], res["batched"]):
-        assert np.array_equal(f11, b11) and np.array_equal(f12, b12)
+    for other in ("batched", "plain"):
+        for (f11, f12), (b11, b12) in zip(res["fused"], res[other]):
+            assert np.array_equal(f11, b11) and np.array_equal(f12, b12)
 
 
 def test_autotune_tries_the_fused_schedule(fdm):
