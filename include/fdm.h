@@ -125,18 +125,21 @@ typedef enum fdm_schedule {
     FDM_SCHEDULE_AUTO = 0,     /* batched launches when n_instances > 1        */
     FDM_SCHEDULE_BATCHED = 1,  /* one launch per stage for all instances       */
     FDM_SCHEDULE_PLAIN = 2,    /* one launch per stage per instance            */
-    FDM_SCHEDULE_FUSED = 3     /* one launch per step per instance: both Heun
-                                  stages in one pass, the first stage's
-                                  densities kept in registers, so a step reads
-                                  and writes the state once (8 B per node each
-                                  way, + 4 B read with a celerity field, against
-                                  20 + 28 B unfused).  FP32 precision,
-                                  time_order 2, semi-discrete scheme only.  The
-                                  same results bit for bit; faster where the
-                                  state exceeds the on-chip cache and the
-                                  unfused launches stream from HBM, slower
-                                  where it fits (about 15-25% more arithmetic:
-                                  halo columns and rows of the first stage)   */
+    FDM_SCHEDULE_FUSED = 3     /* one launch per step (for all instances of a
+                                  context): both stages in one pass, the first
+                                  stage's densities kept in registers, so a
+                                  step reads and writes the state once (8 B
+                                  per node each way, + 4 B read with a
+                                  celerity field, against 20 + 28 B for the
+                                  two stage launches).  FP32 precision,
+                                  time_order 2 (Heun) or 3 (explicit
+                                  midpoint), semi-discrete scheme only.  The
+                                  same results bit for bit.  About 20% more
+                                  arithmetic per node (halo lanes and rows of
+                                  the first stage) but one launch instead of
+                                  two and no stage-buffer traffic: measured
+                                  faster at every size tried, 1.5x beyond the
+                                  on-chip cache.  The autotuner includes it  */
 } fdm_schedule;
 
 /* Precision of the stage kernels.
@@ -331,7 +334,7 @@ typedef struct fdm_tune_trial {
  * tile height in {4, 8, 12, 16, 24, 32, 48, 64} (heights above the tallest
  * instance are skipped) and, for a context created with FDM_SCHEDULE_AUTO,
  * for each schedule that applies: batched and plain (several instances),
- * and fused (FP32 precision, time_order 2, semi-discrete scheme).  The
+ * and fused (FP32 precision, time_order 2 or 3, semi-discrete scheme).  The
  * context then keeps the fastest candidate.  alpha11/alpha12 are read, never
  * written; the step count and diagnostics baseline are unchanged.  Up to
  * max_trials measured candidates are written to trials (may be NULL when

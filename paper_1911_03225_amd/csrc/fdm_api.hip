@@ -255,9 +255,11 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
     if (c->fused) {   // both Heun stages per launch, ping-pong between the state and the stage buffer
         for (int32_t step = 0; step < n_steps; ++step) {
             if (c->batched)
-                FDM_HIP(c, fdm::launch_fused_batched(c->d_inst, c->d_tile_inst, c->total_tiles, step & 1, s));
+                FDM_HIP(c, fdm::launch_fused_batched(c->d_inst, c->d_tile_inst, c->total_tiles, step & 1,
+                                                     c->time_order == 3, s));
             else
-                for (int i = 0; i < c->n; ++i) FDM_HIP(c, fdm::launch_fused(c->inst[i], step & 1, s));
+                for (int i = 0; i < c->n; ++i)
+                    FDM_HIP(c, fdm::launch_fused(c->inst[i], step & 1, c->time_order == 3, s));
         }
     }
     for (int32_t step = 0; step < (c->fused ? 0 : n_steps); ++step) {
@@ -556,9 +558,10 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         order = o;
     }
     if (opt.schedule == FDM_SCHEDULE_FUSED &&
-        !(opt.precision == FDM_PRECISION_FP32 && order == 2 && descs[0].scheme == FDM_SCHEME_SEMIDISCRETE))
+        !(opt.precision == FDM_PRECISION_FP32 && (order == 2 || order == 3) &&
+          descs[0].scheme == FDM_SCHEME_SEMIDISCRETE))
         return fail(nullptr, FDM_ERR_INVALID_ARG,
-                    "the fused schedule needs FP32 precision, time_order 2 and the semi-discrete scheme");
+                    "the fused schedule needs FP32 precision, time_order 2 or 3 and the semi-discrete scheme");
     // Courant bound of a fixed dt needs s_max; uniform cases are checked here,
     // field cases after the device reduction below.
     fdm_ctx *c = new (std::nothrow) fdm_ctx;
@@ -842,7 +845,8 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
     if (c->schedule == FDM_SCHEDULE_AUTO) {
         if (c->n > 1) schedules = {FDM_SCHEDULE_BATCHED, FDM_SCHEDULE_PLAIN};
         else schedules = {FDM_SCHEDULE_PLAIN};
-        if (c->precision == fdm::PREC_FP32 && c->time_order == 2 && !c->fd) schedules.push_back(FDM_SCHEDULE_FUSED);
+        if (c->precision == fdm::PREC_FP32 && (c->time_order == 2 || c->time_order == 3) && !c->fd)
+            schedules.push_back(FDM_SCHEDULE_FUSED);
     } else {
         schedules = {was_fused ? FDM_SCHEDULE_FUSED : was_batched ? FDM_SCHEDULE_BATCHED : FDM_SCHEDULE_PLAIN};
     }

@@ -120,14 +120,15 @@ hipError_t launch_stage(const InstDev &I, int mode, int precision, hipStream_t s
 hipError_t launch_stage_batched(const InstDev *d_inst, const int32_t *d_tile_inst,
                                 int64_t total_tiles, int mode, bool fd, int precision, hipStream_t s);
 hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s);
-// Fused two-stage Heun step of one instance (float state and arithmetic,
-// semi-discrete scheme): dir 0 from the state into the stage buffer, dir 1
-// back; tiles of I.rows rows and 56 columns.
-hipError_t launch_fused(const InstDev &I, int dir, hipStream_t s);
+// Fused two-stage step of one instance (float state and arithmetic,
+// semi-discrete scheme; Heun, or the explicit midpoint when mid): dir 0 from
+// the state into the stage buffer, dir 1 back; tiles of I.rows rows and 56
+// columns.
+hipError_t launch_fused(const InstDev &I, int dir, bool mid, hipStream_t s);
 // The same for every instance of a batched context in one launch (the tile
 // map and tile_begin of the fused tiling).
 hipError_t launch_fused_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles, int dir,
-                                hipStream_t s);
+                                bool mid, hipStream_t s);
 hipError_t launch_stats(const void *a11, const void *a12, int64_t n, int precision,
                         StatsPartial *d_partials, double *d_out, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, int64_t n, int precision, hipStream_t s);

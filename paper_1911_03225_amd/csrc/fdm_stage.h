@@ -734,7 +734,7 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
 // (distinct buffers: neighbouring tiles still read src).
 constexpr int kFStrip = kFusedStrip, kFHalo = 4;
 
-template <int LK, int VK, bool FIELD>
+template <int LK, int VK, bool FIELD, bool MID = false>
 __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int chunk, int lane, const void *src11,
                                                const void *src12, void *dst11, void *dst12)
 {
@@ -742,6 +742,8 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
     using S = float;
     const int nx = I.nx, ny = I.ny;
     const R theta = I.theta, cx = I.cx, cy = I.cy;
+    // explicit midpoint: stage A advances half a step (halving is exact)
+    const R cxa = MID ? 0.5f * cx : cx, cya = MID ? 0.5f * cy : cy;
     const R V1 = I.V1, V2 = I.V2;
 
     const int gcol = strip * kFStrip - kFHalo + lane;
@@ -828,8 +830,8 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
             const R hr = from_right(hv);
             const R hprev = hhA[hp];
             hhA[h] = hv;
-            wxo[p & 3] = S(madd(-cx, hr - hv, wx));          // alpha_12 of row m after stage 1
-            wyo[(p + 3) & 3] = S(madd(cy, hv - hprev, ym1));  // alpha_11 of row m-1 after stage 1
+            wxo[p & 3] = S(madd(-cxa, hr - hv, wx));          // alpha_12 of row m after stage 1
+            wyo[(p + 3) & 3] = S(madd(cya, hv - hprev, ym1));  // alpha_11 of row m-1 after stage 1
             kA = next_row(kA, ny);
         }
         if (it < 4) return;
@@ -851,14 +853,14 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
             const R hr = from_right(hv);
             const R hprev = hhB[hp];
             hhB[h] = hv;
-            {
-                R nv = madd(-cx, hr - hv, wx);
-                nv = madd(R(0.5), b12, R(0.5) * nv);
+            {   // Heun: the mean of the state and one more stage; midpoint: the state plus a full step
+                R nv = madd(-cx, hr - hv, MID ? b12 : wx);
+                if constexpr (!MID) nv = madd(R(0.5), b12, R(0.5) * nv);
                 put(row_ptr<S>(dst12, kB, nx, bi < nrows), off_st, S(nv));
             }
             {
-                R nv = madd(cy, hv - hprev, ym1);
-                nv = madd(R(0.5), b11, R(0.5) * nv);
+                R nv = madd(cy, hv - hprev, MID ? b11 : ym1);
+                if constexpr (!MID) nv = madd(R(0.5), b11, R(0.5) * nv);
                 put(row_ptr<S>(dst11, kBprev, nx, bi > 0), off_st, S(nv));
             }
             kBprev = kB;
@@ -993,7 +995,7 @@ hipError_t launch_stage_t(const InstDev &I, int mode, hipStream_t s)
 
 // Fused Heun step: dir 0 reads the state and writes the stage buffer, dir 1
 // the other way round.
-template <int LK, int VK, bool FIELD>
+template <int LK, int VK, bool FIELD, bool MID>
 __global__ __launch_bounds__(kBlock) void fused_kernel(InstDev I, int64_t total_tiles, int blocks_per_xcd,
                                                        int strips, int dir)
 {
@@ -1002,12 +1004,12 @@ __global__ __launch_bounds__(kBlock) void fused_kernel(InstDev I, int64_t total_
     const int t = (int)tile;
     const void *s11 = dir ? I.w11 : I.a11, *s12 = dir ? I.w12 : I.a12;
     void *d11 = dir ? I.a11 : I.w11, *d12 = dir ? I.a12 : I.w12;
-    run_tile_fused<LK, VK, FIELD>(I, t % strips, t / strips, threadIdx.x & 63, s11, s12, d11, d12);
+    run_tile_fused<LK, VK, FIELD, MID>(I, t % strips, t / strips, threadIdx.x & 63, s11, s12, d11, d12);
 }
 
 // Batched fused step: one launch for the fused tiles of every instance;
 // limiter, Hamiltonian and field presence are per instance (wave-uniform).
-template <int DIR>
+template <int DIR, bool MID>
 __global__ __launch_bounds__(kBlock) void fused_kernel_batched(const InstDev *__restrict__ insts,
                                                                const int32_t *__restrict__ tile_inst,
                                                                int64_t total_tiles, int blocks_per_xcd)
@@ -1022,30 +1024,30 @@ __global__ __launch_bounds__(kBlock) void fused_kernel_batched(const InstDev *__
     void *d11 = DIR ? I.a11 : I.w11, *d12 = DIR ? I.a12 : I.w12;
     const int lk = limiter_kind(I.limiter);
     if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_PRESCRIBED, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_PRESCRIBED, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
         else if (lk == LK_SUPERBEE)
-            run_tile_fused<LK_SUPERBEE, VK_PRESCRIBED, false>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else run_tile_fused<LK_THETA, VK_PRESCRIBED, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+            run_tile_fused<LK_SUPERBEE, VK_PRESCRIBED, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else run_tile_fused<LK_THETA, VK_PRESCRIBED, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
     } else if (I.v0f != nullptr) {
-        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, true>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else if (lk == LK_SUPERBEE) run_tile_fused<LK_SUPERBEE, VK_LAW, true>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else run_tile_fused<LK_THETA, VK_LAW, true>(I, strip, chunk, lane, s11, s12, d11, d12);
+        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, true, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else if (lk == LK_SUPERBEE) run_tile_fused<LK_SUPERBEE, VK_LAW, true, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else run_tile_fused<LK_THETA, VK_LAW, true, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
     } else {
-        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
         else if (lk == LK_SUPERBEE)
-            run_tile_fused<LK_SUPERBEE, VK_LAW, false>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else run_tile_fused<LK_THETA, VK_LAW, false>(I, strip, chunk, lane, s11, s12, d11, d12);
+            run_tile_fused<LK_SUPERBEE, VK_LAW, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else run_tile_fused<LK_THETA, VK_LAW, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
     }
 }
 
-template <int LK, int VK, bool FIELD>
+template <int LK, int VK, bool FIELD, bool MID>
 hipError_t launch_fused_t(const InstDev &I, int dir, hipStream_t s)
 {
     const int strips = (I.nx + kFStrip - 1) / kFStrip;
     const int64_t tiles = (int64_t)strips * ((I.ny + I.rows - 1) / I.rows);
     const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
-    hipLaunchKernelGGL((fused_kernel<LK, VK, FIELD>), dim3(8 * per_xcd), dim3(kBlock), 0, s, I, tiles, per_xcd,
+    hipLaunchKernelGGL((fused_kernel<LK, VK, FIELD, MID>), dim3(8 * per_xcd), dim3(kBlock), 0, s, I, tiles, per_xcd,
                        strips, dir);
     return hipGetLastError();
 }

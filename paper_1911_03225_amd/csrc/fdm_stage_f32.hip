@@ -16,38 +16,53 @@ hipError_t launch_stage_f32(const InstDev &I, int mode, hipStream_t s)
 }
 
 namespace {
+template <bool MID>
 hipError_t launch_fused_r(const InstDev &I, int dir, hipStream_t s)
 {
     const int lk = limiter_kind(I.limiter);
     if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_PRESCRIBED, false>(I, dir, s);
-        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_PRESCRIBED, false>(I, dir, s);
-        return launch_fused_t<LK_THETA, VK_PRESCRIBED, false>(I, dir, s);
+        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_PRESCRIBED, false, MID>(I, dir, s);
+        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_PRESCRIBED, false, MID>(I, dir, s);
+        return launch_fused_t<LK_THETA, VK_PRESCRIBED, false, MID>(I, dir, s);
     }
     if (I.vkind != VK_LAW) return hipErrorInvalidValue;   // semi-discrete scheme only
     if (I.v0f != nullptr) {
-        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, true>(I, dir, s);
-        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, true>(I, dir, s);
-        return launch_fused_t<LK_THETA, VK_LAW, true>(I, dir, s);
+        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, true, MID>(I, dir, s);
+        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, true, MID>(I, dir, s);
+        return launch_fused_t<LK_THETA, VK_LAW, true, MID>(I, dir, s);
     }
-    if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, false>(I, dir, s);
-    if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, false>(I, dir, s);
-    return launch_fused_t<LK_THETA, VK_LAW, false>(I, dir, s);
+    if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, false, MID>(I, dir, s);
+    if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, false, MID>(I, dir, s);
+    return launch_fused_t<LK_THETA, VK_LAW, false, MID>(I, dir, s);
 }
 }  // namespace
 
-hipError_t launch_fused(const InstDev &I, int dir, hipStream_t s) { return launch_fused_r(I, dir, s); }
+hipError_t launch_fused(const InstDev &I, int dir, bool mid, hipStream_t s)
+{
+    return mid ? launch_fused_r<true>(I, dir, s) : launch_fused_r<false>(I, dir, s);
+}
 
 hipError_t launch_fused_batched(const InstDev *d_inst, const int32_t *d_tile_inst, int64_t total_tiles, int dir,
-                                hipStream_t s)
+                                bool mid, hipStream_t s)
 {
     const int64_t blocks = (total_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
     const dim3 grid(8 * per_xcd), block(kBlock);
-    if (dir)
-        hipLaunchKernelGGL(fused_kernel_batched<1>, grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
-    else
-        hipLaunchKernelGGL(fused_kernel_batched<0>, grid, block, 0, s, d_inst, d_tile_inst, total_tiles, per_xcd);
+    if (mid) {
+        if (dir)
+            hipLaunchKernelGGL((fused_kernel_batched<1, true>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles,
+                               per_xcd);
+        else
+            hipLaunchKernelGGL((fused_kernel_batched<0, true>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles,
+                               per_xcd);
+    } else {
+        if (dir)
+            hipLaunchKernelGGL((fused_kernel_batched<1, false>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles,
+                               per_xcd);
+        else
+            hipLaunchKernelGGL((fused_kernel_batched<0, false>), grid, block, 0, s, d_inst, d_tile_inst, total_tiles,
+                               per_xcd);
+    }
     return hipGetLastError();
 }
 

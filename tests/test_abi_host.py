@@ -212,10 +212,9 @@ def test_invalid_options_rejected(fdm):
     (dict(), {"schedule": "fused", "precision": "fp64"}),
     (dict(), {"schedule": "fused", "precision": "fp64_arith"}),
     (dict(time_order=1), {"schedule": "fused"}),
-    (dict(time_order=3), {"schedule": "fused"}),
     (dict(time_order=1, scheme="fully_discrete"), {"schedule": "fused"}),
 ])
-def test_fused_schedule_needs_fp32_heun_semidiscrete(fdm, kw, opts):
+def test_fused_schedule_needs_fp32_two_stage_semidiscrete(fdm, kw, opts):
     with pytest.raises(fdm.FdmError) as e:
         fdm.fdm_transport_init(fdm.desc(16, 16, **kw), options=opts)
     assert e.value.status == fdm.FDM_ERR_INVALID_ARG

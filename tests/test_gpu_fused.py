@@ -50,6 +50,42 @@ def test_fused_equals_unfused_bitwise(fdm, kw, steps):
     _same(f[-1], u[-1])
 
 
+@pytest.mark.parametrize("kw", [CASES[0], CASES[2], CASES[5]])
+@pytest.mark.parametrize("steps", [1, 6, 7])
+def test_fused_midpoint_equals_unfused_bitwise(fdm, kw, steps):
+    """The explicit midpoint (time_order 3) fused the same way: stage A takes
+    half a step, stage B a full one from the step's initial state."""
+    a11, a12 = W.ring(150, 130, R=35.0, sigma=3.0)
+    _, f = gpu_run(a11, a12, steps, options=FUSED, cfl=0.4, time_order=3, **dict(kw))
+    _, u = gpu_run(a11, a12, steps, options={"schedule": "plain"}, cfl=0.4, time_order=3, **dict(kw))
+    _same(f[-1], u[-1])
+
+
+def test_fused_midpoint_batched_and_oracle(fdm, oracle):
+    import torch
+    nx, ny = 192, 128
+    v0 = W.fourier_celerity(nx, ny, np.random.default_rng(3))
+    a11, a12 = W.diagonal_bands(nx, ny, np.random.default_rng(4), n_bands=12)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 200, every=100, options=FUSED, limiter="minmod", cfl=0.4,
+                                v0_field=v0, time_order=3)
+    for s, e1, einf in rep:
+        assert e1 <= tolerance(s), (s, e1, einf)
+    field = to_dev(v0)
+    descs = [fdm.desc(nx, ny, limiter="minmod", cfl=0.4, v0_field=field, time_order=3),
+             fdm.desc(70, 90, limiter="superbee", cfl=0.4, v0=-1.0, time_order=3)]
+    states = [(a11, a12), W.ring(70, 90, R=20.0, sigma=2.0)]
+    res = {}
+    for sched in ("fused", "plain"):
+        t = [(to_dev(a), to_dev(b)) for a, b in states]
+        ctx = fdm.fdm_transport_init(descs, options={"schedule": sched}, keep=[field])
+        fdm.fdm_transport_step(ctx, [x[0] for x in t], [x[1] for x in t], 9)
+        torch.cuda.synchronize()
+        res[sched] = [(x.cpu().numpy(), y.cpu().numpy()) for x, y in t]
+        fdm.fdm_destroy(ctx)
+    for (f11, f12), (p11, p12) in zip(res["fused"], res["plain"]):
+        assert np.array_equal(f11, p11) and np.array_equal(f12, p12)
+
+
 @pytest.mark.parametrize("nx,ny", [(1, 1), (3, 5), (55, 9), (56, 2), (57, 3), (113, 67), (200, 1), (1, 40)])
 def test_fused_odd_sizes_bitwise(fdm, nx, ny):
     rng = np.random.default_rng(nx * 1000 + ny)
