@@ -42,7 +42,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_c2_2048_fp32_traffic
 KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_kernels.hip"]
 STAGE_NAMES = {"fwd": "stage_kernel<float, float, 2, 0, false, 0, false>",
                "heun2": "stage_kernel<float, float, 2, 0, false, 2, false>",
-               "fused": "fused_kernel<2, 0, false>"}
+               "fused": "fused_kernel<2, 0, false, false>"}
 COPY_NAME = "copy_kernel<float>"
 
 
