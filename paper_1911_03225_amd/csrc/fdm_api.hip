@@ -3,8 +3,9 @@
 // Host-side responsibilities: validate descriptors before any HIP call,
 // compute the CFL-bounded step from max |v0| (a device reduction for a
 // celerity field), own the per-instance stage buffers and reduction
-// scratch, sequence the stage launches (two per Heun step), replay captured
-// HIP graphs for fdm_run, and keep a sticky error per context.
+// scratch, sequence the stage launches (two per Heun step, or one fused
+// launch), replay captured HIP graphs for fdm_run, and keep a sticky error
+// per context.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
