@@ -192,3 +192,25 @@ def test_autotune_tries_the_fused_schedule(fdm):
     trials = fdm.fdm_autotune(ctx, [s11], [s12], trial_steps=1)
     assert {t["schedule"] for t in trials} == {"plain"}
     fdm.fdm_destroy(ctx)
+
+
+def test_coupled_run_on_a_fused_context(fdm):
+    """A context created with the fused schedule still runs coupled steps
+    (they use the stage kernels with their per-tile Hhat sums), with the same
+    bits as a plain context."""
+    import torch
+    phi, a11, a12 = W.plateau_rings(96, 80, seed=2, count=4, rmin=8.0, rmax=20.0)
+    out = []
+    for sched in ("fused", "plain"):
+        t11, t12 = to_dev(a11), to_dev(a12)
+        ctx = fdm.fdm_transport_init(fdm.desc(96, 80, limiter="minmod", cfl=0.4, v0=-1.0),
+                                     options={"schedule": sched})
+        L = fdm.loading(strain_rate13=2e-3, tau0=0.005, mobility=1.0, mu=1.0, lam=1.5, layer_h=3.0,
+                        cell_l3=24.0, dt_max=0.25, eps13=0.02, phi_mean=float(phi.mean()))
+        hist = fdm.fdm_run(ctx, t11, t12, 20, 10, loading=L)
+        fdm.fdm_transport_step(ctx, t11, t12, 3)      # and uncoupled steps after it
+        torch.cuda.synchronize()
+        out.append((t11.cpu().numpy(), t12.cpu().numpy(), [h[0]["phi_mean"] for h in hist]))
+        fdm.fdm_destroy(ctx)
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
