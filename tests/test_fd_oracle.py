@@ -154,6 +154,23 @@ def test_x_only_data_matches_printed_1d_scheme(oracle, theta, c):
         assert np.max(np.abs(inc[r] - (new - phi))) < 1e-14
 
 
+@pytest.mark.parametrize("c", [-1.0, 0.7])
+def test_y_only_data_matches_printed_1d_scheme(oracle, c):
+    """The same along y, with dx != dy: alpha_11 = -d2 phi, so w_y = -alpha_11
+    carries the 1-D profile and the y pieces use dy."""
+    rng = np.random.default_rng(27)
+    n, dx, dy, dt, theta = 80, 1.3, 0.6, 0.15, 1.5
+    y = np.arange(n) * dy
+    L = n * dy
+    phi = np.cos(2 * np.pi * y / L) + 0.4 * np.abs(np.sin(4 * np.pi * y / L)) + 0.05 * rng.normal(size=n)
+    new = _printed_1d_step(phi, dy, dt, theta, lambda p: c * np.abs(p), lambda p: c * np.sign(p))
+    a11 = np.tile((-(np.roll(phi, -1) - phi) / dy)[:, None], (1, 3))
+    F = _fd(oracle, 3, n, dx=dx, dy=dy, limiter="theta", theta=theta, v0=c, dt=dt)
+    inc = oracle.fd_increment_field(F, a11, np.zeros((n, 3)))
+    for col in range(3):
+        assert np.max(np.abs(inc[:, col] - (new - phi))) < 1e-14
+
+
 # -------------------------------------------------------------- invariants
 
 @pytest.mark.parametrize("limiter", ["minmod", "mc", "superbee"])
