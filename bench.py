@@ -274,36 +274,45 @@ def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
     """The spatially varying celerity workload: 4096^2 diagonal bands (64
     bands, seed 3) under a Fourier-mode celerity field, minmod, Heun, CFL
     0.45.  State, stage buffer and field (320 MiB) exceed the 256 MB MALL, so
-    this is the HBM-side figure; a device-to-device copy of the same bytes
-    per step is timed beside it as the practical streaming peak."""
+    this is the HBM-side figure.  The plain schedule (two stage launches per
+    step, 48 B per node with the field) is timed beside the autotuned one,
+    and a device-to-device copy of the same bytes per step as the practical
+    streaming peak."""
     import torch
     a11, a12, v0 = workloads.c3_bands(n, seed=3)
     dev = torch.device("cuda:0")
-    t11, t12 = torch.from_numpy(a11).to(dev), torch.from_numpy(a12).to(dev)
     tv = torch.from_numpy(v0).to(dev)
     stream = torch.cuda.current_stream()
-    ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter="minmod", cfl=0.45, v0_field=tv), stream=stream,
-                                 keep=[tv])
-    sched = "plain"
-    if autotune:
-        trials = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=5)
-        sched = min(trials, key=lambda t: t["seconds_per_step"])["schedule"]
-    rows = fdm.fdm_tile_rows(ctx, 0)
-    fdm.fdm_run(ctx, t11, t12, K, K)          # captures the chunk graph
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(3):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        fdm.fdm_run(ctx, t11, t12, K, K)
-        e1.record(stream)
+
+    def timed(schedule, tune):
+        t11, t12 = torch.from_numpy(a11).to(dev), torch.from_numpy(a12).to(dev)
+        ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter="minmod", cfl=0.45, v0_field=tv),
+                                     options={"schedule": schedule}, stream=stream, keep=[tv])
+        sched = "plain" if schedule == "auto" else schedule   # untuned AUTO keeps the two stage launches
+        if tune:
+            trials = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=5)
+            sched = min(trials, key=lambda t: t["seconds_per_step"])["schedule"]
+        rows = fdm.fdm_tile_rows(ctx, 0)
+        fdm.fdm_run(ctx, t11, t12, K, K)          # captures the chunk graph
         torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1) / 1000.0)
-    fdm.fdm_destroy(ctx)
-    t = sorted(times)[1]
+        times = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fdm.fdm_run(ctx, t11, t12, K, K)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1000.0)
+        fdm.fdm_destroy(ctx)
+        del t11, t12
+        return sorted(times)[1], rows, sched
+
+    t, rows, sched = timed("auto", autotune)
+    tp, rows_p, _ = timed("plain", False)
     value = n * n * K / t
-    # reference: copy the bytes one step must move at least (unfused stages:
-    # 48 B per node with the field) with a plain device-to-device copy
+    plain = n * n * K / tp
+    # reference: copy the bytes one unfused step must move at least (48 B per
+    # node with the field) with a plain device-to-device copy
     nbytes = 48 * n * n
     src = torch.empty(nbytes // 8, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -319,12 +328,18 @@ def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
     del src, dst
     alg = value * 20 / 1e9     # algorithmic bytes per cell-update with a field: 20
     unfused = value * 48 / 1e9
-    log("bench[c3]: %dx%d %.3e cell-updates/s (%d-row tiles, %s), copy reference %.0f GB/s" %
-        (n, n, value, rows, sched, copy_gbs))
+    plain_gbs = plain * 48 / 1e9
+    log("bench[c3]: %dx%d %.3e cell-updates/s (%d-row tiles, %s); plain %.3e (%.0f GB/s, %.2f of HBM peak); "
+        "copy reference %.0f GB/s" % (n, n, value, rows, sched, plain, plain_gbs, plain_gbs / HBM_PEAK_GBS,
+                                      copy_gbs))
     return {"grid": [n, n], "limiter": "minmod", "cfl": 0.45, "steps": K, "tile_rows": rows, "schedule": sched,
             "ms_per_step": round(1e3 * t / K, 4), "cell_updates_per_s": round(value, 1),
             "hbm_frac_algorithmic": round(alg / HBM_PEAK_GBS, 4),
             "unfused_stream_gbs": round(unfused, 1),
+            "plain": {"tile_rows": rows_p, "ms_per_step": round(1e3 * tp / K, 4),
+                      "cell_updates_per_s": round(plain, 1), "stream_gbs": round(plain_gbs, 1),
+                      "hbm_frac": round(plain_gbs / HBM_PEAK_GBS, 4),
+                      "bytes_per_cell_update": 48},
             "copy_reference_gbs": round(copy_gbs, 1),
             "unfused_stream_frac_of_copy": round(unfused / copy_gbs, 4),
             "timing": "HIP events around graph-replayed chunks, median of 3; copy: torch device copy of the same "

@@ -332,7 +332,11 @@ typedef struct fdm_tune_trial {
  * changes no result bit, only speed).  Copies the given state into scratch
  * memory, and on that copy times trial_steps (>= 1) steps for each candidate
  * tile height in {4, 8, 12, 16, 24, 32, 48, 64} (heights above the tallest
- * instance are skipped) and, for a context created with FDM_SCHEDULE_AUTO,
+ * instance are skipped) and each balanced height: for k = 1 .. 8, the
+ * smallest height (at most 512) whose largest launch has at most k waves
+ * per SIMD of the device (a wave per tile; four SIMDs per compute unit),
+ * so that the SIMDs carry equal work; and, for a context created with
+ * FDM_SCHEDULE_AUTO,
  * for each schedule that applies: batched and plain (several instances),
  * and fused (FP32 precision, time_order 2 or 3, semi-discrete scheme).  The
  * context then keeps the fastest candidate.  alpha11/alpha12 are read, never

@@ -174,10 +174,9 @@ float round_down_float(double x)
 // launch should give every SIMD about six waves (6144 on 256 CUs x 4 SIMDs)
 // to hide memory latency.  `strip_rows` is the number of (strip, row) pairs
 // the launch covers (over all instances of a batched launch).  The result
-// is that count / 6144 rounded up to a multiple of 4 and kept in [4, 32].
-// Measured on MI355X (superbee, Heun): 1024^2 is fastest with 4 rows,
-// 2048^2 with 12 (16 is 6% slower), 4096^2 and 8192^2 with 32 (64 is 6-9%
-// slower).
+// is that count / 6144 rounded up to a multiple of 4 and kept in [4, 16]
+// (1024^2: 4 rows, 2048^2: 12, larger grids: 16).  The autotuner times
+// fixed and SIMD-balanced heights beside it.
 int pick_rows(int64_t strip_rows, int ny, int requested)
 {
     if (requested > 0) return std::min(requested, ny);
@@ -191,9 +190,43 @@ int pick_rows(int64_t strip_rows, int ny, int requested)
     return (int)std::min<int64_t>(rows, ny);
 }
 
+// Tallest balanced height the autotuner tries (one round of waves over a
+// 8192^2 grid needs 149 rows).
+constexpr int kMaxBalancedRows = 512;
+
 int64_t strip_rows_of(const fdm_transport_desc &d)
 {
     return (int64_t)((d.nx + fdm::kStrip - 1) / fdm::kStrip) * d.ny;
+}
+
+// Waves (one per tile) of the largest launch a step makes with the given
+// tile height: every instance's tiles for a batched launch, the largest
+// instance's for one launch per instance.
+int64_t launch_waves(const fdm_ctx *c, bool fused, bool batched, int rows)
+{
+    int64_t total = 0, largest = 0;
+    for (const fdm_transport_desc &d : c->desc) {
+        const int r = std::min(rows, d.ny);
+        const int w = fused ? fdm::kFusedStrip : fdm::kStrip;
+        const int64_t t = (int64_t)((d.nx + w - 1) / w) * ((d.ny + r - 1) / r);
+        total += t;
+        largest = std::max(largest, t);
+    }
+    return batched ? total : largest;
+}
+
+// Smallest tile height whose launch has at most `limit` waves, or -1 if even
+// one tile per strip exceeds it.  launch_waves falls as the height grows.
+int balanced_rows(const fdm_ctx *c, bool fused, bool batched, int max_ny, int64_t limit)
+{
+    if (launch_waves(c, fused, batched, max_ny) > limit) return -1;
+    int lo = 1, hi = max_ny;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (launch_waves(c, fused, batched, mid) <= limit) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 void release(fdm_ctx *c)
@@ -831,6 +864,11 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
             return fail(c, e == hipErrorOutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE,
                         std::string("hipMalloc: ") + hipGetErrorString(e));
     }
+    // SIMDs of the device (four per compute unit), for the balanced heights
+    int dev = 0, cus = 0;
+    FDM_HIP(c, hipGetDevice(&dev));
+    FDM_HIP(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t simds = 4 * (int64_t)std::max(cus, 1);
     std::vector<void *> s11(c->n), s12(c->n);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool was_batched = c->batched, was_fused = c->fused;
@@ -867,8 +905,21 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
         for (int sched : schedules) {
             const bool fused = sched == FDM_SCHEDULE_FUSED;
             const bool batched = sched == FDM_SCHEDULE_BATCHED || (fused && c->n > 1);
-            for (int rows : {4, 8, 12, 16, 24, 32, 48, 64}) {
-                if (rows > max_ny && rows != 4) continue;
+            // Fixed heights, then balanced ones.  A launch of at most eight
+            // waves per SIMD is resident at once and its waves carry equal
+            // work, so the SIMD holding the most waves sets its time: the
+            // smallest height with at most k waves per SIMD (k = 1 .. 8)
+            // evens the SIMDs out at the least halo work for k rounds.
+            std::vector<int> heights;
+            for (int rows : {4, 8, 12, 16, 24, 32, 48, 64})
+                if (rows <= max_ny || rows == 4) heights.push_back(rows);
+            for (int k = 1; k <= 8; ++k) {
+                const int rows = balanced_rows(c, fused, batched, max_ny, k * simds);
+                if (rows > 0 && rows <= kMaxBalancedRows &&
+                    std::find(heights.begin(), heights.end(), rows) == heights.end())
+                    heights.push_back(rows);
+            }
+            for (int rows : heights) {
                 c->batched = batched;
                 c->fused = fused;
                 fdm_status r = retile(c, rows);

@@ -51,6 +51,47 @@ def _setup(F, cases, schedule, precision="fp32"):
     return ctx, t11, t12
 
 
+FIXED = {4, 8, 12, 16, 24, 32, 48, 64}
+
+
+def _simds():
+    import torch
+    return 4 * torch.cuda.get_device_properties(0).multi_processor_count
+
+
+def _balanced_heights(cases, fused, batched, simds):
+    """For k = 1..8 the smallest tile height whose largest launch has at most
+    k waves (one per tile) per SIMD, by trying every height."""
+    width = 56 if fused else 60
+    max_ny = max(c["ny"] for c in cases)
+
+    def waves(rows):
+        t = [-(-c["nx"] // width) * -(-c["ny"] // min(rows, c["ny"])) for c in cases]
+        return sum(t) if batched else max(t)
+    out = set()
+    for k in range(1, 9):
+        fits = [r for r in range(1, max_ny + 1) if waves(r) <= k * simds]
+        if fits and fits[0] <= 512:
+            out.add(fits[0])
+    return out
+
+
+def _expected_heights(cases, schedule):
+    max_ny = max(c["ny"] for c in cases)
+    fixed = {r for r in FIXED if r <= max_ny or r == 4}
+    fused = schedule == "fused"
+    batched = schedule == "batched" or (fused and len(cases) > 1)
+    return fixed | _balanced_heights(cases, fused, batched, _simds())
+
+
+def test_balanced_heights_of_a_large_grid():
+    """The helper itself on 2048^2 (no device call): one, two, ... waves per
+    SIMD of 1024 SIMDs at the smallest height that fits."""
+    case = [dict(nx=2048, ny=2048)]
+    assert _balanced_heights(case, True, False, 1024) == {76, 38, 25, 19, 15, 13, 11, 10}
+    assert _balanced_heights(case, False, False, 1024) == {71, 36, 24, 18, 15, 12, 11, 9}
+
+
 def _host(ts):
     return [t.cpu().numpy() for t in ts]
 
@@ -68,7 +109,8 @@ def test_autotune_single_instance(fdm, precision):
     assert all(np.array_equal(x, y) for x, y in zip(before, after)), "autotune wrote the caller's state"
     # FP32 Heun contexts also time the fused launches
     assert {t["schedule"] for t in trials} == ({"plain", "fused"} if precision == "fp32" else {"plain"})
-    assert {t["tile_rows"] for t in trials} == {4, 8, 12, 16, 24, 32, 48, 64}
+    for sched in {t["schedule"] for t in trials}:
+        assert {t["tile_rows"] for t in trials if t["schedule"] == sched} == _expected_heights(case, sched)
     best = min(trials, key=lambda t: t["seconds_per_step"])
     assert fdm.fdm_tile_rows(ctx, 0) == best["tile_rows"]
     assert all(t["seconds_per_step"] > 0 for t in trials)
@@ -92,8 +134,10 @@ def test_autotune_batched_schedules(fdm):
     ctx, t11, t12 = _setup(fdm, cases, "auto")
     trials = fdm.fdm_autotune(ctx, t11, t12, trial_steps=2)
     assert {t["schedule"] for t in trials} == {"batched", "plain", "fused"}
-    # candidates above the tallest instance (200 rows) are skipped
-    assert max(t["tile_rows"] for t in trials) == 64
+    # fixed candidates above the tallest instance (200 rows) are skipped
+    for sched in ("batched", "plain", "fused"):
+        assert {t["tile_rows"] for t in trials if t["schedule"] == sched} == _expected_heights(cases, sched)
+    assert max(t["tile_rows"] for t in trials) <= 200
     best = min(trials, key=lambda t: t["seconds_per_step"])
     for i, c in enumerate(cases):
         assert fdm.fdm_tile_rows(ctx, i) == min(best["tile_rows"], c["ny"])
