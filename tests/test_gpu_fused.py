@@ -129,6 +129,39 @@ def test_fused_ring_oracle_parity(fdm, oracle):
         assert e1 <= tolerance(s), (s, e1, einf)
 
 
+def test_c2_full_size_fused_balanced_heights(fdm, oracle):
+    """C2 at full size (2048^2 loop, superbee, Courant 0.4) in the launch
+    shapes the benchmark runs: the fused schedule at the SIMD-balanced tile
+    heights 15 and 19 (graph-replayed chunks), 12 steps against the oracle,
+    and bit for bit equal to each other."""
+    from gpu_util import oracle_problem, rel_l1
+    a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
+    runs = []
+    for rows in (15, 19):
+        runs.append(_run_chunks(fdm, a11, a12, 12, 6, {"schedule": "fused", "tile_rows": rows},
+                                limiter="superbee", cfl=0.4, v0=-1.0))
+    (dt, g11, g12), (dt2, h11, h12) = runs
+    assert dt == dt2
+    assert np.array_equal(g11, h11) and np.array_equal(g12, h12)
+    P = oracle_problem(oracle, 2048, 2048, dt, limiter="superbee", cfl=0.4, v0=-1.0)
+    o11, o12 = oracle.run(P, a11.astype(np.float64), a12.astype(np.float64), 12)
+    e1 = rel_l1(g11, g12, o11, o12, a11, a12)
+    assert e1 <= tolerance(12), e1
+
+
+def _run_chunks(F, a11, a12, steps, chunk, options, **kw):
+    import torch
+    ny, nx = a11.shape
+    t11, t12 = to_dev(a11), to_dev(a12)
+    ctx = F.fdm_transport_init(F.desc(nx, ny, **kw), options=options)
+    assert F.fdm_tile_rows(ctx, 0) == options["tile_rows"]
+    F.fdm_run(ctx, t11, t12, steps, chunk)
+    torch.cuda.synchronize()
+    dt = F.fdm_transport_dt(ctx)
+    F.fdm_destroy(ctx)
+    return dt, t11.cpu().numpy().astype(np.float64), t12.cpu().numpy().astype(np.float64)
+
+
 @pytest.mark.parametrize("chunk", [5, 8])
 def test_fused_graph_chunks_bitwise(fdm, chunk):
     """fdm_run replays captured chunks (odd chunks end with the copy back)."""
