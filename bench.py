@@ -92,7 +92,8 @@ def _counter_means(directories, counter):
             continue
         _, grid[k], v = max(groups)
         out[k] = sum(v) / len(v)
-    return out, grid
+    by_grid = {(fam, g): sum(v) / len(v) for (fam, g), v in vals.items()}
+    return out, grid, by_grid
 
 
 def rows_from_grid(grid_threads, n, strip=60):
@@ -113,14 +114,22 @@ def write_traffic_summary(fetch_dir, write_dir, out, copy_n, grid_n):
     """Per-launch traffic of the two stage kernels from counter passes.  The
     copy kernel reads and writes 4*copy_n^2 bytes: the ratio to what each
     counter reports for it is that counter's calibration factor."""
-    fetch, grid = _counter_means(fetch_dir, "FETCH_SIZE")
-    write, _ = _counter_means(write_dir, "WRITE_SIZE")
+    fetch, grid, fetch_g = _counter_means(fetch_dir, "FETCH_SIZE")
+    write, _, write_g = _counter_means(write_dir, "WRITE_SIZE")
     copy_kib = 4.0 * copy_n * copy_n / 1024.0
     ff, wf = copy_kib / fetch["copy"], copy_kib / write["copy"]
     per = {k: {"fetch_kib": round(fetch[k], 1), "write_kib": round(write[k], 1),
                "bytes": round((fetch[k] * ff + write[k] * wf) * 1024.0),
                "tile_rows": rows_from_grid(grid[k], grid_n, 56 if k == "fused" else 60)}
            for k in STAGE_NAMES if k in fetch and k in write}
+    # the fused step at every tile height the passes ran (the autotuner's
+    # choice varies between balanced heights of equal speed)
+    fused_by_rows = {}
+    for (fam, g), fk in sorted(fetch_g.items()):
+        if fam == "fused" and (fam, g) in write_g:
+            wk = write_g[(fam, g)]
+            fused_by_rows[str(rows_from_grid(g, grid_n, 56))] = {
+                "fetch_kib": round(fk, 1), "write_kib": round(wk, 1), "bytes": round((fk * ff + wk * wf) * 1024.0)}
     unfused = [per[k]["bytes"] for k in ("fwd", "heun2") if k in per]
     summary = {"kernel_source_sha256": kernel_source_hash(), "grid": grid_n,
                "tile_rows": per["fwd"]["tile_rows"] if "fwd" in per else None,
@@ -129,7 +138,8 @@ def write_traffic_summary(fetch_dir, write_dir, out, copy_n, grid_n):
                "copy_fetch_kib": round(fetch["copy"], 1), "copy_write_kib": round(write["copy"], 1),
                "stage": per,
                "bytes_per_launch": round(sum(unfused) / len(unfused)) if len(unfused) == 2 else None,
-               "fused_bytes_per_launch": per["fused"]["bytes"] if "fused" in per else None}
+               "fused_bytes_per_launch": per["fused"]["bytes"] if "fused" in per else None,
+               "fused_by_rows": fused_by_rows}
     with open(out, "w") as fh:
         json.dump(summary, fh, indent=1)
     print(json.dumps(summary))
@@ -140,8 +150,8 @@ def load_traffic(grid_n, precision, limiter, tile_rows, fused=False):
     workload, or None when no summary was measured on the current kernel
     sources and configuration.  Unfused: the average of the two stage
     launches, at the same tile height as the timed launches.  Fused: the
-    one launch per step; the autotuner's height may differ from the
-    profiled one (reported beside it)."""
+    one launch per step, at the timed height when the passes covered it,
+    else at the profiled one (reported beside it)."""
     if precision != "fp32" or limiter != "superbee" or not os.path.exists(TRAFFIC_FILE):
         return None
     try:
@@ -152,6 +162,9 @@ def load_traffic(grid_n, precision, limiter, tile_rows, fused=False):
     if t.get("kernel_source_sha256") != kernel_source_hash() or t.get("grid") != grid_n:
         return None
     if fused:
+        f = t.get("fused_by_rows", {}).get(str(tile_rows))
+        if f:
+            return f["bytes"], tile_rows
         f = t.get("stage", {}).get("fused")
         return (f["bytes"], f["tile_rows"]) if f else None
     if t.get("tile_rows") != tile_rows or not t.get("bytes_per_launch"):
