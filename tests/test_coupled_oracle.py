@@ -152,3 +152,69 @@ def test_fully_discrete_slip_matches_the_phi_form():
     e = CP.coupled_run(a11, a12, 6, 6, tau0=0.005, eps13=0.02, phi_mean=pm, **kn)
     assert np.max(np.abs(f[0] - e[0])) < 1e-13 and np.max(np.abs(f[1] - e[1])) < 1e-13
     assert f[2][-1]["phi_mean"] == pytest.approx(e[2][-1]["phi_mean"], abs=1e-13)
+
+
+def test_explicit_midpoint_slip_matches_the_phi_form():
+    """Explicit midpoint: phi^{n+1} = phi - dt Hhat(u + dt/2 L(u)).  Its
+    differences are the densities the midpoint transport produced, and its
+    mean is the tracked mean slip."""
+    phi, _, _ = _rings(seed=7)
+    ph = phi.copy()
+    a12 = np.roll(ph, -1, axis=1) - ph
+    a11 = -(np.roll(ph, -1, axis=0) - ph)
+    eps, pm = 0.02, float(phi.mean())
+    ny, nx = a11.shape
+    c11, c12 = a11.copy(), a12.copy()
+    for _ in range(6):
+        tau = S.static_tau13(c11, c12, 1.0, 1.0, 1.0, 1.5, 3, 24, eps, pm)
+        v0 = (-CP.soft_threshold(tau, 0.005)).astype(np.float32).astype(np.float64)
+        vmax = np.max(np.abs(v0))
+        dt = CP.round_down_float(min(0.4 / vmax, KW["dt_max"]) if vmax > 0 else KW["dt_max"])
+        P = T.Problem(nx, ny, limiter="minmod", v0=v0, time_order=3, dt=dt)
+        Ph = T.Problem(nx, ny, limiter="minmod", v0=v0, time_order=1, dt=0.5 * dt)
+        h11, h12 = T.run(Ph, c11, c12, 1)
+        H = T.hhat_field(P, h11, h12)
+        ph = ph - dt * H
+        c11, c12 = T.run(P, c11, c12, 1)
+        pm -= dt * H.mean()
+        eps += KW["strain_rate13"] * dt
+    d12 = np.roll(ph, -1, axis=1) - ph
+    d11 = -(np.roll(ph, -1, axis=0) - ph)
+    assert np.max(np.abs(d12 - c12)) < 1e-13 and np.max(np.abs(d11 - c11)) < 1e-13
+    kw = dict(KW, time_order=3)
+    b11, b12, hist = CP.coupled_run(a11, a12, 6, 6, tau0=0.005, eps13=0.02, phi_mean=float(phi.mean()), **kw)
+    assert np.array_equal(b11, c11) and np.array_equal(b12, c12)
+    assert hist[-1]["phi_mean"] == pytest.approx(pm, abs=1e-15)
+
+
+@pytest.mark.parametrize("law", ["threshold", "wiggly"])
+def test_celerity_of_a_density_free_layer(law):
+    """No densities: tau13 is the mean stress 2 mu eps13 - mu (h/L3) <phi>
+    everywhere and phi = <phi> at every node, so the celerity is the law
+    evaluated by hand (threshold: -m S(tau); wiggly: m (tau_y cos(phi/beta)
+    - tau)), the step min(cfl dx / max|v0|, dt_max) rounded down to float32,
+    and nothing moves."""
+    import math
+    ny, nx = 6, 8
+    z = np.zeros((ny, nx))
+    mu, eps, pm, m = 0.8, 0.013, 0.02, 0.7
+    kw = dict(KW, mu=mu, lam=1.2, mobility=m, dt_max=100.0)
+    tau = 2 * mu * eps - mu * pm * 3 / 24
+    if law == "wiggly":
+        v = m * (0.03 * math.cos(pm / 0.007) - tau)
+        run = CP.coupled_run(z, z, 1, 1, law="wiggly", tau_y=0.03, beta=0.007, eps13=eps, phi_mean=pm, **kw)
+    else:
+        v = -m * math.copysign(max(abs(tau) - 0.004, 0.0), tau)
+        run = CP.coupled_run(z, z, 1, 1, tau0=0.004, eps13=eps, phi_mean=pm, **kw)
+    b11, b12, hist = run
+    vmax = abs(float(np.float32(v)))
+    assert vmax > 0.0
+    r = hist[-1]
+    assert r["vmax"] == vmax
+    dt = float(np.float32(0.4 / vmax))
+    if dt > 0.4 / vmax:
+        dt = float(np.nextafter(np.float32(dt), np.float32(0)))
+    assert r["dt"] == dt and dt <= 0.4 / vmax and r["t"] == dt
+    assert np.all(b11 == 0.0) and np.all(b12 == 0.0) and r["phi_mean"] == pm
+    assert r["eps13"] == pytest.approx(eps + KW["strain_rate13"] * dt, rel=1e-15)
+    assert r["sigma13"] == pytest.approx(2 * mu * r["eps13"] - mu * pm * 3 / 24, rel=1e-14)
