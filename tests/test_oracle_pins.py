@@ -308,6 +308,20 @@ def test_cfl_dt(oracle):
     assert oracle.cfl_dt(Q, 0.5) == 0.5
 
 
+def _f32_down(x):
+    f = np.float32(x)
+    return float(np.nextafter(f, np.float32(0)) if float(f) > x else f)
+
+
+@pytest.mark.parametrize("V", [(0.7, -0.4), (-0.2, 0.9), (0.0, 0.3)])
+def test_cfl_dt_prescribed_per_axis(oracle, V):
+    """Prescribed velocity on unequal spacings: the step is nu over the
+    larger per-axis rate |V_i| / dx_i, rounded down to float32."""
+    P = oracle.Problem(8, 8, dx=1.3, dy=0.6, vkind="prescribed", V=V)
+    want = 0.5 / max(abs(V[0]) / 1.3, abs(V[1]) / 0.6)
+    assert oracle.cfl_dt(P, 0.5) == _f32_down(want)
+
+
 def test_paper_time_steps_golden(oracle):
     """The paper's printed grid spacings and time steps (sec. 4.3, 4.4.1)."""
     with open(os.path.join(GOLDEN, "paper_runs.json")) as f:
