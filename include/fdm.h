@@ -114,10 +114,12 @@ typedef struct fdm_transport_desc {
                                 float), rejected with FDM_ERR_CFL if
                                 dt s_max / min(dx,dy) > 1                        */
     int32_t velocity;        /* fdm_velocity                                    */
-    double v0;               /* LAW: uniform celerity when v0_field is NULL     */
+    double v0;               /* LAW: uniform celerity when v0_field is NULL,
+                                rounded to float (the kernels' and s_max's)     */
     const float *v0_field;   /* LAW: device array of nx*ny node celerities, or
                                 NULL; s_max = max |v0| over the field           */
-    double V[2];             /* PRESCRIBED: velocity (V1, V2)                   */
+    double V[2];             /* PRESCRIBED: velocity (V1, V2), rounded to
+                                float; s_max = max(|V1|/dx, |V2|/dy) min(dx,dy)  */
 } fdm_transport_desc;
 
 /* Scheduling options; pass NULL for the defaults. */

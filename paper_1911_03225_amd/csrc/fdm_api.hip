@@ -648,7 +648,8 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         const double h = std::min(d.dx, d.dy);
         double smax;
         if (d.velocity == FDM_VELOCITY_PRESCRIBED) {
-            smax = std::max(std::fabs(d.V[0]) / d.dx, std::fabs(d.V[1]) / d.dy) * h;
+            // the float32 velocity the kernels use, as for a uniform celerity
+            smax = std::max(std::fabs((double)(float)d.V[0]) / d.dx, std::fabs((double)(float)d.V[1]) / d.dy) * h;
         } else if (d.v0_field) {
             INIT_HIP(fdm::launch_absmax(d.v0_field, n, c->d_absmax, c->stream));
             INIT_HIP(hipMemcpyAsync(absmax.data(), c->d_absmax, sizeof(float) * fdm::kAbsmaxBlocks,

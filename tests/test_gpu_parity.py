@@ -609,3 +609,37 @@ def test_midpoint_tile_rows_schedules_and_graph_bitwise(fdm, precision):
     for k, v in res.items():
         for (a, b), (c_, d) in zip(v, ref):
             assert np.array_equal(a, c_) and np.array_equal(b, d), k
+
+
+# ------------------------------------------------------------- step size
+
+STEP_CASES = [
+    dict(nx=32, ny=24, dx=1.0, dy=1.0, cfl=0.4, v0=-1.0),
+    dict(nx=32, ny=24, dx=0.7, dy=1.9, cfl=0.45, v0=2.3),
+    dict(nx=40, ny=16, dx=1.3, dy=0.6, cfl=0.5, velocity="prescribed", V=(0.7, -0.4)),
+    dict(nx=40, ny=16, dx=1.3, dy=0.6, cfl=0.3, velocity="prescribed", V=(-0.2, 0.9)),
+    dict(nx=40, ny=16, dx=0.9, dy=0.9, cfl=1.0, velocity="prescribed", V=(1.0, 0.5)),
+    dict(nx=64, ny=48, dx=1.1, dy=0.8, cfl=0.45, field=True),
+    dict(nx=8, ny=8, dx=1.0, dy=1.0, cfl=0.4, v0=0.0),
+]
+
+
+@pytest.mark.parametrize("case", STEP_CASES)
+def test_step_size_equals_oracle(fdm, oracle, case):
+    """The CFL step (the largest float32 not above nu min(dx, dy) / s_max,
+    s_max per axis for a prescribed velocity, max |v0| of a celerity field
+    by a device reduction) is the oracle's, bit for bit."""
+    kw = dict(case)
+    nx, ny = kw.pop("nx"), kw.pop("ny")
+    field = None
+    if kw.pop("field", False):
+        field = W.fourier_celerity(nx, ny, np.random.default_rng(17), kmax=2).astype(np.float32)
+        kw["v0_field"] = to_dev(field)
+    ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, **kw), keep=[kw["v0_field"]] if field is not None else [])
+    dt = fdm.fdm_transport_dt(ctx)
+    fdm.fdm_destroy(ctx)
+    vkind = "prescribed" if kw.get("velocity") == "prescribed" else "law"
+    f32 = lambda x: float(np.float32(x))   # the library takes velocities as float32
+    P = oracle.Problem(nx, ny, dx=kw["dx"], dy=kw["dy"], vkind=vkind, V=tuple(map(f32, kw.get("V", (0.0, 0.0)))),
+                       v0=field.astype(np.float64) if field is not None else f32(kw.get("v0", -1.0)))
+    assert dt == oracle.cfl_dt(P, kw["cfl"])
