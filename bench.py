@@ -33,6 +33,12 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Hamiltonians with gradients (32), four speeds (16), weights (12), the
 # weighted sum and viscosity terms (19), update and stage combination (9).
 OPS_PER_NODE_STAGE = 120
+# VALU instructions the compiled node function (LAW, superbee) issues per
+# node-stage: SQ_INSTS_VALU per wave over the node-stages the wave computes,
+# 85 for the fused kernel's loop and the stage kernel alike.  Fewer than the
+# operations of the definition: FMA, med3 and three-operand max/min each do
+# two or three of them in one issue.
+ISSUED_PER_NODE_STAGE = 85
 
 
 # Per-launch memory traffic of the stage kernel, measured with rocprofv3
@@ -507,7 +513,13 @@ def main():
                 # measured L2-to-fabric bytes (counter passes) over this run's launch time;
                 # at 2048^2 the working set sits in the 256 MB MALL, which serves much of it
                 "fabric_achieved_gbs": round(tr[0] / kernel_s / 1e9, 1) if tr else None,
-                "fabric_frac_of_hbm_peak": round(tr[0] / kernel_s / 1e9 / HBM_PEAK_GBS, 4) if tr else None}
+                "fabric_frac_of_hbm_peak": round(tr[0] / kernel_s / 1e9 / HBM_PEAK_GBS, 4) if tr else None,
+                # the same launch counted in issued instructions: the node-stages
+                # the step needs (halo lanes and rows left out) at the compiled
+                # code's instruction count, over the issue peak
+                "issue_view": {"valu_instr_per_node_stage": ISSUED_PER_NODE_STAGE,
+                               "useful_issue_frac": round(ISSUED_PER_NODE_STAGE * cells * stages_per_launch
+                                                          / kernel_s / 1e12 / ALU_PEAK_TOPS, 4)}}
     final = hist[-1][0]
     fdm.fdm_destroy(ctx)
 
