@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -114,14 +115,17 @@ std::string check_desc(const fdm_transport_desc &d)
     if (d.scheme != FDM_SCHEME_SEMIDISCRETE && d.scheme != FDM_SCHEME_FULLY_DISCRETE) return "unknown scheme";
     if (d.scheme == FDM_SCHEME_FULLY_DISCRETE && d.time_order > 1)
         return "the fully discrete scheme is one pass per step: time_order must be 0 or 1";
-    if (!(std::isfinite(d.dt) && d.dt >= 0.0)) return "dt must be finite and >= 0";
+    if (!(std::isfinite(d.dt) && d.dt >= 0.0 && d.dt <= (double)FLT_MAX))
+        return "dt must be finite (as a float) and >= 0";
     if (d.dt == 0.0 && !(d.cfl > 0.0 && d.cfl <= 1.0)) return "cfl must lie in (0, 1]";
     if (d.velocity != FDM_VELOCITY_LAW && d.velocity != FDM_VELOCITY_PRESCRIBED)
         return "unknown velocity kind";
-    if (d.velocity == FDM_VELOCITY_LAW && d.v0_field == nullptr && !std::isfinite(d.v0))
-        return "v0 must be finite";
-    if (d.velocity == FDM_VELOCITY_PRESCRIBED && !(std::isfinite(d.V[0]) && std::isfinite(d.V[1])))
-        return "V must be finite";
+    // the kernels take velocities as float: they must stay finite there
+    const auto float_finite = [](double v) { return std::isfinite(v) && std::fabs(v) <= (double)FLT_MAX; };
+    if (d.velocity == FDM_VELOCITY_LAW && d.v0_field == nullptr && !float_finite(d.v0))
+        return "v0 must be finite (as a float)";
+    if (d.velocity == FDM_VELOCITY_PRESCRIBED && !(float_finite(d.V[0]) && float_finite(d.V[1])))
+        return "V must be finite (as a float)";
     return "";
 }
 

@@ -105,9 +105,12 @@ BAD = [
     (dict(cfl=0.0), "cfl"),
     (dict(cfl=1.5), "cfl"),
     (dict(dt=-1.0), "dt"),
+    (dict(dt=1e39, v0=0.0), "dt"),
     (dict(velocity=5), "velocity"),
     (dict(v0=float("inf")), "v0"),
     (dict(velocity="prescribed", V=(float("nan"), 0.0)), "V"),
+    (dict(v0=1e39), "v0"),
+    (dict(velocity="prescribed", V=(0.5, -4e38)), "V"),
     (dict(scheme=5), "scheme"),
     (dict(scheme="fully_discrete", time_order=2), "one pass per step"),
     (dict(scheme="fully_discrete", time_order=3), "one pass per step"),
