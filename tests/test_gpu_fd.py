@@ -180,3 +180,14 @@ def test_fd_batched_equals_plain(fdm, oracle):
         o11, o12 = oracle.run(P, a11, a12, 25)
         g11, g12 = results["batched"][i]
         assert rel_l1(g11, g12, o11, o12, a11, a12) <= tolerance(25)
+
+
+@pytest.mark.parametrize("rows", [9, 16])
+def test_fd_c2_full_size_short(fdm, oracle, rows):
+    """The benchmark's fully discrete leg at full size: the 2048^2 loop,
+    superbee, Courant 0.25, 10 steps, at a SIMD-balanced tile height (9) and
+    the default rule's (16)."""
+    a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
+    dt, rep, g, o = compare_run(oracle, a11, a12, 10, every=5, options={"tile_rows": rows},
+                                limiter="superbee", cfl=0.25, v0=-1.0, **FD)
+    _assert_report(rep)

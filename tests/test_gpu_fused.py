@@ -149,6 +149,27 @@ def test_c2_full_size_fused_balanced_heights(fdm, oracle):
     assert e1 <= tolerance(12), e1
 
 
+def test_c3_full_size_fused_equals_plain(fdm):
+    """The celerity-field workload at full size (4096^2 bands under a
+    Fourier celerity, minmod, Courant 0.45) in the benchmark's launch shape:
+    the fused schedule at 50-row tiles gives the plain schedule's bits after
+    an odd number of steps (the last copied back from the stage buffer)."""
+    import torch
+    a11, a12, v0 = W.c3_bands(4096, seed=3)
+    tv = to_dev(v0)
+    out = []
+    for opts in ({"schedule": "fused", "tile_rows": 50}, {"schedule": "plain"}):
+        t11, t12 = to_dev(a11), to_dev(a12)
+        ctx = fdm.fdm_transport_init(fdm.desc(4096, 4096, limiter="minmod", cfl=0.45, v0_field=tv),
+                                     options=opts, keep=[tv])
+        fdm.fdm_run(ctx, t11, t12, 3, 3)
+        torch.cuda.synchronize()
+        out.append((t11.cpu().numpy(), t12.cpu().numpy()))
+        fdm.fdm_destroy(ctx)
+        del t11, t12
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def _run_chunks(F, a11, a12, steps, chunk, options, **kw):
     import torch
     ny, nx = a11.shape
