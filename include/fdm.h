@@ -54,7 +54,7 @@ typedef enum fdm_status {
     FDM_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed                     */
     FDM_ERR_CFL = 4,           /* a fixed dt exceeds the Courant-number-1 bound   */
     FDM_ERR_NONFINITE = 5,     /* a NaN or Inf was found in the densities         */
-    FDM_ERR_UNSUPPORTED = 6    /* feature not available in this build             */
+    FDM_ERR_UNSUPPORTED = 6    /* feature not available                           */
 } fdm_status;
 
 /* Step 1 limiters (sec. 3.2.2, limited second difference of U^p_13, i.e.

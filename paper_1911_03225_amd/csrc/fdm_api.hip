@@ -1004,7 +1004,7 @@ const char *fdm_status_string(fdm_status s)
     case FDM_ERR_OUT_OF_MEMORY: return "out of device memory";
     case FDM_ERR_CFL: return "time step above the Courant-number-1 bound";
     case FDM_ERR_NONFINITE: return "non-finite densities";
-    case FDM_ERR_UNSUPPORTED: return "unsupported in this build";
+    case FDM_ERR_UNSUPPORTED: return "unsupported";
     }
     return "unknown status";
 }
