@@ -44,7 +44,7 @@ ISSUED_PER_NODE_STAGE = 85
 # Per-launch memory traffic of the stage kernel, measured with rocprofv3
 # counters (FETCH_SIZE and WRITE_SIZE passes, each calibrated by a plain copy
 # kernel of known size) and tied to the kernel sources it was measured on.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_c2_2048_fp32_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage_kernel_loop_2048_fp32_traffic.json")
 KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_kernels.hip"]
 STAGE_NAMES = {"fwd": "stage_kernel<float, float, 2, 0, false, 0, false>",
                "heun2": "stage_kernel<float, float, 2, 0, false, 2, false>",
@@ -191,14 +191,14 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
     import numpy as np
     import torch
 
-    insts = workloads.c5_instances()
+    insts = workloads.batched_instances()
     t0 = time.perf_counter()
     workers = max(1, min(16, os.cpu_count() or 1))
     import multiprocessing as mp
     # fresh worker interpreters: this process already holds a GPU context
     with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         arrays = list(ex.map(_make_instance, insts, chunksize=4))
-    log("bench[c5]: generated %d instances in %.1f s" % (len(insts), time.perf_counter() - t0))
+    log("bench[batched]: generated %d instances in %.1f s" % (len(insts), time.perf_counter() - t0))
     dev = torch.device("cuda:0")
     base11 = [torch.from_numpy(a[0]).to(dev) for a in arrays]
     base12 = [torch.from_numpy(a[1]).to(dev) for a in arrays]
@@ -215,7 +215,7 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
         ctx = fdm.fdm_transport_init(descs, options={"schedule": sched}, stream=stream, keep=fields)
         if autotune:
             trials = fdm.fdm_autotune(ctx, s11, s12, trial_steps=2)
-            log("bench[c5]: %s autotune: %s" % (sched, ", ".join("%d rows %.3f ms" % (
+            log("bench[batched]: %s autotune: %s" % (sched, ", ".join("%d rows %.3f ms" % (
                 t["tile_rows"], 1e3 * t["seconds_per_step"]) for t in trials)))
         rows[sched] = fdm.fdm_tile_rows(ctx, 0)
         if sched != "plain":
@@ -245,7 +245,7 @@ def batched_vs_plain(fdm, workloads, K, log, autotune=True):
                       "tile_rows": rows[sched],
                       "nonfinite_instances": sum(1 for st in stats if st["nonfinite"])}
         finals[sched] = (s11, s12)
-        log("bench[c5]: %s %d steps in %.3f s (%.3e cell-updates/s)" % (sched, K, dt_s, nodes * K / dt_s))
+        log("bench[batched]: %s %d steps in %.3f s (%.3e cell-updates/s)" % (sched, K, dt_s, nodes * K / dt_s))
     def same(a, b):
         return all(torch.equal(x, y) for x, y in zip(finals[a][0], finals[b][0])) and \
             all(torch.equal(x, y) for x, y in zip(finals[a][1], finals[b][1]))
@@ -279,7 +279,7 @@ def coupled_leg(fdm, workloads, n_steps, log, n=512):
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     fdm.fdm_destroy(ctx)
-    log("bench[c4]: %d coupled steps in %.3f s (%.1f us/step)" % (n_steps, sec, 1e6 * sec / n_steps))
+    log("bench[coupled]: %d coupled steps in %.3f s (%.1f us/step)" % (n_steps, sec, 1e6 * sec / n_steps))
     return {"grid": [n, n], "steps": n_steps, "seconds": round(sec, 4),
             "ms_per_step": round(1e3 * sec / n_steps, 4),
             "cell_updates_per_s": round(n * n * n_steps / sec, 1),
@@ -289,7 +289,7 @@ def coupled_leg(fdm, workloads, n_steps, log, n=512):
             "stress_strain_columns": ["eps13", "sigma13", "phi_mean", "vmax"]}
 
 
-def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
+def celerity_field_leg(fdm, workloads, K, log, n=4096, autotune=True):
     """The spatially varying celerity workload: 4096^2 diagonal bands (64
     bands, seed 3) under a Fourier-mode celerity field, minmod, Heun, CFL
     0.45.  State, stage buffer and field (320 MiB) exceed the 256 MB MALL, so
@@ -298,7 +298,7 @@ def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
     and a device-to-device copy of the same bytes per step as the practical
     streaming peak."""
     import torch
-    a11, a12, v0 = workloads.c3_bands(n, seed=3)
+    a11, a12, v0 = workloads.bands_and_celerity(n, seed=3)
     dev = torch.device("cuda:0")
     tv = torch.from_numpy(v0).to(dev)
     stream = torch.cuda.current_stream()
@@ -348,7 +348,7 @@ def c3_leg(fdm, workloads, K, log, n=4096, autotune=True):
     alg = value * 20 / 1e9     # algorithmic bytes per cell-update with a field: 20
     unfused = value * 48 / 1e9
     plain_gbs = plain * 48 / 1e9
-    log("bench[c3]: %dx%d %.3e cell-updates/s (%d-row tiles, %s); plain %.3e (%.0f GB/s, %.2f of HBM peak); "
+    log("bench[field]: %dx%d %.3e cell-updates/s (%d-row tiles, %s); plain %.3e (%.0f GB/s, %.2f of HBM peak); "
         "copy reference %.0f GB/s" % (n, n, value, rows, sched, plain, plain_gbs, plain_gbs / HBM_PEAK_GBS,
                                       copy_gbs))
     return {"grid": [n, n], "limiter": "minmod", "cfl": 0.45, "steps": K, "tile_rows": rows, "schedule": sched,
@@ -410,14 +410,14 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep --tile-rows instead of timing the candidate tilings first (fdm_autotune)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64_arith", "fp64"])
-    ap.add_argument("--no-c5", action="store_true", help="skip the batched-vs-plain measurement")
-    ap.add_argument("--c5-steps", type=int, default=500)
-    ap.add_argument("--no-c4", action="store_true", help="skip the coupled-run measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--no-coupled", action="store_true", help="skip the coupled-run measurement")
     ap.add_argument("--no-fd", action="store_true", help="skip the fully-discrete-scheme measurement")
-    ap.add_argument("--no-c3", action="store_true", help="skip the 4096^2 celerity-field measurement")
+    ap.add_argument("--no-field", action="store_true", help="skip the 4096^2 celerity-field measurement")
     ap.add_argument("--schedule", default="auto", choices=["auto", "plain", "fused"],
                     help="launch schedule of the main workload (auto: the autotuner may pick fused)")
-    ap.add_argument("--c4-steps", type=int, default=5000)
+    ap.add_argument("--coupled-steps", type=int, default=5000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="N",
                     help="also run one single-stage (Euler) step on an N x N zero state: its copy-back is a "
                          "plain copy kernel reading and writing 4*N*N bytes per array, the byte reference for "
@@ -535,17 +535,17 @@ def main():
         del z11, z12
         log("bench: copy probe: one Euler step on %dx%d, copy kernel of %d bytes per array" % (m, m, 4 * m * m))
 
-    c5 = None
-    if not args.no_c5:
-        c5 = batched_vs_plain(fdm, workloads, args.c5_steps, log, autotune=not args.no_autotune)
+    batched_leg = None
+    if not args.no_batched:
+        batched_leg = batched_vs_plain(fdm, workloads, args.batched_steps, log, autotune=not args.no_autotune)
 
-    c4 = None
-    if not args.no_c4:
-        c4 = coupled_leg(fdm, workloads, args.c4_steps, log)
+    coupled_run_leg = None
+    if not args.no_coupled:
+        coupled_run_leg = coupled_leg(fdm, workloads, args.coupled_steps, log)
 
-    c3 = None
-    if not args.no_c3:
-        c3 = c3_leg(fdm, workloads, 100, log, autotune=not args.no_autotune)
+    field_leg = None
+    if not args.no_field:
+        field_leg = celerity_field_leg(fdm, workloads, 100, log, autotune=not args.no_autotune)
 
     fd = None
     if not args.no_fd:
@@ -584,10 +584,10 @@ def main():
         "hbm_frac_algorithmic": round(value * BYTES_PER_CELL_STEP / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "batched_vs_plain": c5,
-        "coupled": c4,
+        "batched_vs_plain": batched_leg,
+        "coupled": coupled_run_leg,
         "fully_discrete": fd,
-        "celerity_field_4096": c3,
+        "celerity_field_4096": field_leg,
         "final_stats": {"step": final["step"], "sum_abs": final["sum_abs"], "max_norm": final["max_norm"],
                         "drift11": final["drift11"], "drift12": final["drift12"]},
     }

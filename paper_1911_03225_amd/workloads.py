@@ -27,9 +27,9 @@ import numpy as np
 from scipy.special import erf as _verf, erfc as _verfc
 
 __all__ = [
-    "densities_from_phi", "c1_collision", "c1_exact_period", "smooth_sine",
+    "densities_from_phi", "colliding_pulses", "exact_period_profile", "smooth_sine",
     "ring", "square_loop", "half_square_waves", "diagonal_bands",
-    "fourier_celerity", "c3_bands", "Instance", "c5_instances",
+    "fourier_celerity", "bands_and_celerity", "Instance", "batched_instances",
 ]
 
 def densities_from_phi(phi: np.ndarray, dx: float = 1.0, dy: float = 1.0):
@@ -45,7 +45,7 @@ def _step_profile(xi: np.ndarray, sigma: float) -> np.ndarray:
     return -sigma * sqrt(pi / 2.0) * _verfc(xi / (sigma * sqrt(2.0)))
 
 
-def c1_collision(n: int = 64, sigma: float = 4.0, x_neg: float = 20.0, x_pos: float = 44.0):
+def colliding_pulses(n: int = 64, sigma: float = 4.0, x_neg: float = 20.0, x_pos: float = 44.0):
     """Two opposite-sign Gaussian pulses of alpha_12 (amplitude 1) on an n x n grid.
 
     phi(x) = sum over images of [Psi(x - x_pos) - Psi(x - x_neg)]: a well that a
@@ -60,9 +60,9 @@ def c1_collision(n: int = 64, sigma: float = 4.0, x_neg: float = 20.0, x_pos: fl
     return densities_from_phi(phi)
 
 
-def c1_exact_period(n: int = 64):
+def exact_period_profile(n: int = 64):
     """x-only data for the exact-return check of the first-order scheme."""
-    return c1_collision(n)
+    return colliding_pulses(n)
 
 
 def smooth_sine(n: int, L: float = 1.0):
@@ -228,7 +228,7 @@ def fourier_celerity(nx: int, ny: int, rng: np.random.Generator, v0: float = 1.0
     return (v0 * np.tanh(tau / tau0)).astype(np.float32)
 
 
-def c3_bands(n: int = 4096, seed: int = 3):
+def bands_and_celerity(n: int = 4096, seed: int = 3):
     """Spatially varying celerity workload: diagonal bands + Fourier celerity."""
     rng = np.random.default_rng(seed)
     a11, a12 = diagonal_bands(n, n, rng)
@@ -258,18 +258,18 @@ class Instance:
             a11, a12 = diagonal_bands(self.nx, self.ny, rng)
         v0f = None
         if self.velocity == "fourier":
-            # the C3 recipe's wave vectors (|k| <= 8 per 4096 cells) scaled
+            # the 4096^2 field's wave vectors (|k| <= 8 per 4096 cells) scaled
             # to this grid
             kmax = max(1, int(round(8 * min(self.nx, self.ny) / 4096)))
             v0f = fourier_celerity(self.nx, self.ny, rng, kmax=kmax)
         return a11, a12, v0f
 
 
-C5_SIZES = ((64, 64), (128, 128), (256, 512), (512, 512), (1024, 1024), (1024, 2048))
-C5_COUNTS = (128, 96, 64, 48, 32, 16)
+BATCH_SIZES = ((64, 64), (128, 128), (256, 512), (512, 512), (1024, 1024), (1024, 2048))
+BATCH_COUNTS = (128, 96, 64, 48, 32, 16)
 
 
-def c5_instances(seed: int = 5, counts=C5_COUNTS, sizes=C5_SIZES):
+def batched_instances(seed: int = 5, counts=BATCH_COUNTS, sizes=BATCH_SIZES):
     """The batched workload: 384 instances of six sizes (weights 8:6:4:3:2:1).
 
     Per instance, drawn in order from default_rng(seed): limiter in

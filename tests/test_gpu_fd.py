@@ -37,9 +37,9 @@ def _assert_report(report):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64_arith", "fp64"])
 @pytest.mark.parametrize("limiter", ["minmod", "mc", "superbee"])
-def test_fd_c1_collision(fdm, oracle, limiter, precision):
+def test_fd_colliding_pulses(fdm, oracle, limiter, precision):
     """64x64 opposite Gaussian pulses, LAW v0 = -1, 400 steps."""
-    a11, a12 = W.c1_collision(64)
+    a11, a12 = W.colliding_pulses(64)
     dt, rep, g, o = compare_run(oracle, a11, a12, 400, every=100, options={"precision": precision},
                                 limiter=limiter, cfl=0.25, v0=-1.0, **FD)
     _assert_report(rep)
@@ -183,7 +183,7 @@ def test_fd_batched_equals_plain(fdm, oracle):
 
 
 @pytest.mark.parametrize("rows", [9, 16])
-def test_fd_c2_full_size_short(fdm, oracle, rows):
+def test_fd_loop_2048_short(fdm, oracle, rows):
     """The benchmark's fully discrete leg at full size: the 2048^2 loop,
     superbee, Courant 0.25, 10 steps, at a SIMD-balanced tile height (9) and
     the default rule's (16)."""

@@ -129,8 +129,8 @@ def test_fused_ring_oracle_parity(fdm, oracle):
         assert e1 <= tolerance(s), (s, e1, einf)
 
 
-def test_c2_full_size_fused_balanced_heights(fdm, oracle):
-    """C2 at full size (2048^2 loop, superbee, Courant 0.4) in the launch
+def test_loop_2048_fused_balanced_heights(fdm, oracle):
+    """The 2048^2 loop (superbee, Courant 0.4) in the launch
     shapes the benchmark runs: the fused schedule at the SIMD-balanced tile
     heights 15 and 19 (graph-replayed chunks), 12 steps against the oracle,
     and bit for bit equal to each other."""
@@ -149,13 +149,13 @@ def test_c2_full_size_fused_balanced_heights(fdm, oracle):
     assert e1 <= tolerance(12), e1
 
 
-def test_c3_full_size_fused_equals_plain(fdm):
+def test_bands_field_4096_fused_equals_plain(fdm):
     """The celerity-field workload at full size (4096^2 bands under a
     Fourier celerity, minmod, Courant 0.45) in the benchmark's launch shape:
     the fused schedule at 50-row tiles gives the plain schedule's bits after
     an odd number of steps (the last copied back from the stage buffer)."""
     import torch
-    a11, a12, v0 = W.c3_bands(4096, seed=3)
+    a11, a12, v0 = W.bands_and_celerity(4096, seed=3)
     tv = to_dev(v0)
     out = []
     for opts in ({"schedule": "fused", "tile_rows": 50}, {"schedule": "plain"}):

@@ -31,21 +31,21 @@ def _assert_report(report, n_total):
         assert e1 <= tolerance(s), "step %d: rel L1 %.3e (rel Linf %.3e)" % (s, e1, einf)
 
 
-# --------------------------------------------------------------- C1 family
+# -------------------------------------------------- colliding pulses, 64^2
 
 @pytest.mark.parametrize("limiter", ["minmod", "mc", "superbee"])
-def test_c1_collision(fdm, oracle, limiter):
+def test_colliding_pulses(fdm, oracle, limiter):
     """64x64, opposite Gaussian pulses, LAW v0 = -1, Courant 0.5, 400 steps."""
-    a11, a12 = W.c1_collision(64)
+    a11, a12 = W.colliding_pulses(64)
     dt, rep, g, o = compare_run(oracle, a11, a12, 400, every=100, limiter=limiter, cfl=0.5, v0=-1.0)
     assert dt == 0.5
     _assert_report(rep, 400)
     assert not np.any(g[0])                      # alpha_11 stays exactly 0
 
 
-def test_c1_exact_period(fdm, oracle):
+def test_exact_period(fdm, oracle):
     """First order, one stage, Courant 1, V = (1, 0.5): exact return after 64 steps."""
-    a11, a12 = W.c1_exact_period(64)
+    a11, a12 = W.exact_period_profile(64)
     dt, rep, g, o = compare_run(oracle, a11, a12, 64, every=16, limiter="none", time_order=1,
                                 velocity="prescribed", V=(1.0, 0.5), cfl=1.0)
     assert dt == 1.0
@@ -60,11 +60,11 @@ def test_single_stage_odd_even(fdm, oracle, steps):
     _assert_report(rep, steps)
 
 
-# ------------------------------------------------------------ ring (C2)
+# ------------------------------------------------------------- expanding loop
 
 @pytest.mark.parametrize("limiter", ["superbee", "mc"])
 def test_ring_1000_steps(fdm, oracle, limiter):
-    """C2 shape at 256^2 (R = 50, sigma = 6), Courant 0.4, 1000 steps."""
+    """The expanding loop at 256^2 (R = 50, sigma = 6), Courant 0.4, 1000 steps."""
     a11, a12 = W.ring(256, 256, R=50.0, sigma=6.0)
     dt, rep, g, o = compare_run(oracle, a11, a12, 1000, every=100, limiter=limiter, cfl=0.4, v0=-1.0)
     assert dt == float(np.nextafter(np.float32(0.4), np.float32(0)))
@@ -72,8 +72,8 @@ def test_ring_1000_steps(fdm, oracle, limiter):
 
 
 @pytest.mark.parametrize("limiter", ["superbee", "mc"])
-def test_c2_full_size_short(fdm, oracle, limiter):
-    """C2 at its full size (2048^2, R = 300, sigma = 6) for 12 steps, full grid."""
+def test_loop_2048_short(fdm, oracle, limiter):
+    """The loop at its full size (2048^2, R = 300, sigma = 6) for 12 steps, full grid."""
     a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
     dt, rep, g, o = compare_run(oracle, a11, a12, 12, every=6, limiter=limiter, cfl=0.4, v0=-1.0)
     _assert_report(rep, 12)
@@ -98,8 +98,8 @@ def _both_precisions(oracle, a11, a12, snaps, **kw):
 
 
 @pytest.mark.timeout(300)
-def test_c2_full_size_500_steps(fdm, oracle):
-    """C2 at full size for 500 steps: float64 state within 1e-5, FP32 within
+def test_loop_2048_500_steps(fdm, oracle):
+    """The 2048^2 loop for 500 steps: float64 state within 1e-5, FP32 within
     its float32-state bound."""
     a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
     rows = _both_precisions(oracle, a11, a12, [100, 250, 500], limiter="superbee", cfl=0.4, v0=-1.0)
@@ -109,8 +109,8 @@ def test_c2_full_size_500_steps(fdm, oracle):
 
 
 @pytest.mark.timeout(300)
-def test_c2_scaled_full_length(fdm, oracle):
-    """C2 scaled to 1024^2 (R = 150) for the full 2000 steps: the loop meets
+def test_loop_1024_full_length(fdm, oracle):
+    """The loop scaled to 1024^2 (R = 150) for the full 2000 steps: the loop meets
     its periodic images near step 905 and annihilates along the cell edges."""
     a11, a12 = W.ring(1024, 1024, R=150.0, sigma=6.0)
     rows = _both_precisions(oracle, a11, a12, [500, 1000, 1500, 2000], limiter="mc", cfl=0.4, v0=-1.0)
@@ -127,8 +127,8 @@ def _mean_radius(a11, a12, n):
     return float((w * r).sum() / w.sum())
 
 
-def test_c2_full_length_properties(fdm):
-    """C2 for its full 2000 steps (t ~ 800, past the collision with the
+def test_loop_2048_full_length_properties(fdm):
+    """The 2048^2 loop for its full 2000 steps (t ~ 800, past the collision with the
     periodic images at t ~ 724): finite, conserved totals, the loop's radius
     follows R + |v0| t and its peak density is kept (no damping, sec. 4.4.1)
     before the collision."""
@@ -159,10 +159,10 @@ def test_c2_full_length_properties(fdm):
     assert 0.95 < peak < 1.2, peak
 
 
-# ------------------------------------------------- varying celerity (C3)
+# ------------------------------------------------------ varying celerity
 
-def test_c3_shape_parity(fdm, oracle):
-    """Diagonal bands + Fourier celerity field, the C3 recipe scaled to 512^2
+def test_bands_field_shape_parity(fdm, oracle):
+    """Diagonal bands + Fourier celerity field, the 4096^2 recipe scaled to 512^2
     (wave vectors |k| <= 8 per 4096 cells become |k| <= 1), minmod, Courant
     0.45, 300 steps."""
     rng = np.random.default_rng(3)
@@ -173,9 +173,9 @@ def test_c3_shape_parity(fdm, oracle):
     _assert_report(rep, 300)
 
 
-def test_c3_full_size_short(fdm, oracle):
-    """C3 at its full size (4096^2) for 4 steps, full grid."""
-    a11, a12, v0 = W.c3_bands(4096, seed=3)
+def test_bands_field_4096_short(fdm, oracle):
+    """Bands under a celerity field at full size (4096^2) for 4 steps, full grid."""
+    a11, a12, v0 = W.bands_and_celerity(4096, seed=3)
     dt, rep, g, o = compare_run(oracle, a11, a12, 4, every=2, limiter="minmod", cfl=0.45, v0_field=v0)
     assert dt <= 0.45 / np.abs(v0).max()
     _assert_report(rep, 4)
@@ -276,7 +276,7 @@ def test_tile_rows_bitwise_all_kernels(fdm, limiter, kind, precision):
 
 
 def test_deterministic(fdm):
-    a11, a12, v0 = W.c3_bands(512, seed=7)
+    a11, a12, v0 = W.bands_and_celerity(512, seed=7)
     r1 = gpu_run(a11, a12, 50, limiter="minmod", cfl=0.45, v0_field=v0)[1][-1]
     r2 = gpu_run(a11, a12, 50, limiter="minmod", cfl=0.45, v0_field=v0)[1][-1]
     assert np.array_equal(r1[1], r2[1]) and np.array_equal(r1[2], r2[2])
@@ -286,7 +286,7 @@ def test_deterministic(fdm):
 
 def test_stats_match_oracle(fdm, oracle):
     from paper_1911_03225_amd import fdm as F
-    a11, a12, v0 = W.c3_bands(1024, seed=11)
+    a11, a12, v0 = W.bands_and_celerity(1024, seed=11)
     t11, t12 = to_dev(a11), to_dev(a12)
     vf = to_dev(v0)
     ctx = F.fdm_transport_init(F.desc(1024, 1024, limiter="minmod", cfl=0.45, v0_field=vf), keep=[vf])
@@ -383,7 +383,7 @@ FP32_LOOP_BOUND = fp32_loop_bound(100)
 
 def _shock_cases():
     cases = []
-    for inst in W.c5_instances():
+    for inst in W.batched_instances():
         if inst.nx == 64 and inst.init == "bands" and inst.velocity == "uniform" and len(cases) < 3:
             a11, a12, _ = inst.make()
             cases.append(("c5-bands-%s" % inst.limiter, a11, a12, inst.limiter, inst.v0, 500))
@@ -463,12 +463,12 @@ def test_error_paths(fdm):
     F.fdm_destroy(ctx)
 
 
-# ----------------------------------------------- batched workload (C5)
+# ---------------------------------------------------------- batched workload
 
-def _c5_subset():
+def _batched_subset():
     """One instance per (size, velocity, limiter) of the batched recipe."""
     seen, out = set(), []
-    for inst in W.c5_instances():
+    for inst in W.batched_instances():
         key = (inst.nx, inst.ny, inst.velocity, inst.limiter)
         if key not in seen:
             seen.add(key)
@@ -477,13 +477,13 @@ def _c5_subset():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_c5_subset_batched(fdm, oracle, precision):
+def test_batched_subset(fdm, oracle, precision):
     """fp64: float64 state, 1e-5 for every instance.  fp32: the FP32 bar for
     the instance kind (see FP32_LOOP_BOUND and FP32_SHOCK_BOUND)."""
     import torch
     from paper_1911_03225_amd import fdm as F
     steps = 100
-    insts = _c5_subset()
+    insts = _batched_subset()
     arrays = [i.make() for i in insts]
     keep, descs, t11, t12 = [], [], [], []
     for i, (a11, a12, v) in zip(insts, arrays):
@@ -514,11 +514,11 @@ def test_c5_subset_batched(fdm, oracle, precision):
 
 def _bitwise_cases():
     cases = []
-    a11, a12 = W.c1_collision(64)
+    a11, a12 = W.colliding_pulses(64)
     cases.append(("c1-collision", a11, a12, dict(limiter="minmod", cfl=0.5, v0=-1.0), 100))
     a11, a12 = W.ring(130, 70, R=17.5, sigma=2.0)
     cases.append(("ring-collision", a11, a12, dict(limiter="superbee", cfl=0.4, v0=-1.0), 60))
-    for inst in W.c5_instances():
+    for inst in W.batched_instances():
         if inst.nx == 128 and inst.init == "bands" and inst.velocity == "uniform" and inst.limiter == "mc":
             a11, a12, _ = inst.make()
             cases.append(("c5-bands-mc", a11, a12, dict(limiter="mc", cfl=0.4, v0=inst.v0), 100))

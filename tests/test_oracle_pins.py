@@ -210,7 +210,7 @@ def test_discrete_div_alpha_stays_zero(oracle):
 def test_first_order_exact_period(oracle):
     """NONE limiter, one Euler stage, Courant number 1, V = (1, 0.5), x-only data:
     each step shifts alpha_12 by one cell, so n steps return it exactly."""
-    a11, a12 = W.c1_exact_period(64)
+    a11, a12 = W.exact_period_profile(64)
     P = oracle.Problem(64, 64, limiter="none", vkind="prescribed", V=(1.0, 0.5), time_order=1)
     P.dt = oracle.cfl_dt(P, 1.0)
     assert P.dt == 1.0
@@ -424,7 +424,7 @@ def test_square_loop_closing_returns_polygon(oracle):
 def test_tvd_1d(oracle, limiter):
     """Total variation of alpha_12 never grows and no new extrema appear."""
     n = 64
-    a11, a12 = W.c1_collision(n)
+    a11, a12 = W.colliding_pulses(n)
     a11, a12 = a11[:1].astype(np.float64), a12[:1].astype(np.float64)
     P = oracle.Problem(n, 1, limiter=limiter, v0=-1.0)
     P.dt = oracle.cfl_dt(P, 0.5)
