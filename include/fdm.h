@@ -164,7 +164,9 @@ typedef enum fdm_precision {
 
 typedef struct fdm_options {
     int32_t schedule;        /* fdm_schedule                                    */
-    int32_t tile_rows;       /* rows per wave tile; 0 picks a default           */
+    int32_t tile_rows;       /* rows per wave tile; 0 picks a default (fused:
+                                at most five waves per SIMD where that gives
+                                4 to 64 rows); results do not depend on it    */
     int32_t fused;           /* reserved, must be 0                             */
     int32_t precision;       /* fdm_precision                                   */
 } fdm_options;

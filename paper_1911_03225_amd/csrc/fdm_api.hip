@@ -71,6 +71,7 @@ struct fdm_ctx {
     size_t elem = sizeof(float);            // bytes per state value
     int64_t tile_capacity = 0;              // entries of d_tile_inst
     int32_t requested_rows = 0;             // tile rows asked for (0: default rule)
+    int64_t simds = 1024;                   // SIMDs of the device (4 per compute unit)
     bool sticky = false;
     std::string err;
 };
@@ -342,7 +343,21 @@ fdm_status enqueue_steps(fdm_ctx *c, int32_t n_steps, hipStream_t s)
 fdm_status retile(fdm_ctx *c, int requested)
 {
     int64_t batch_strip_rows = 0;
-    for (int i = 0; i < c->n; ++i) batch_strip_rows += strip_rows_of(c->desc[i]);
+    int max_ny = 0;
+    for (int i = 0; i < c->n; ++i) {
+        batch_strip_rows += strip_rows_of(c->desc[i]);
+        max_ny = std::max(max_ny, c->desc[i].ny);
+    }
+    // The fused launch's default: the smallest height with at most five
+    // waves per SIMD, so every SIMD carries the same number of tiles (the
+    // autotuner's balanced heights; five per SIMD is within 1% of the best
+    // at 2048^2 and 4096^2).  The unfused rule where that height is below 4
+    // rows (small grids: the first stage's four extra rows would dominate)
+    // or above 64.
+    if (requested <= 0 && c->fused) {
+        const int r = balanced_rows(c, true, c->batched, max_ny, 5 * c->simds);
+        if (r >= 4 && r <= 64) requested = r;
+    }
     int64_t tile = 0;
     for (int i = 0; i < c->n; ++i) {
         const fdm_transport_desc &d = c->desc[i];
@@ -488,6 +503,12 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
     const fdm::LawParams law{wiggly, L.tau0, L.mobility, L.tau_y, L.beta, L.mobility_field};
     if (!w.v0) FDM_HIP(c, hipMalloc((void **)&w.v0, sizeof(float) * n));
     InstDev I = c->inst[0];
+    if (c->fused && c->requested_rows <= 0) {
+        // the stage kernels' default tiling, as on a plain context: the per-tile
+        // sums then add in the same order whatever the schedule
+        I.rows = pick_rows(strip_rows_of(d), d.ny, 0);
+        I.chunks = (d.ny + I.rows - 1) / I.rows;
+    }
     const int64_t tiles = (int64_t)I.strips * I.chunks;
     if (tiles > w.cap) {
         if (w.d_hsum) FDM_HIP(c, hipFree(w.d_hsum));
@@ -637,6 +658,12 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
     for (int i = 0; i < n_instances; ++i) total += 2 * (int64_t)descs[i].nx * descs[i].ny;
     const size_t elem = opt.precision == FDM_PRECISION_FP64 ? sizeof(double) : sizeof(float);
     c->elem = elem;
+    {
+        int dev = 0, cus = 0;
+        INIT_HIP(hipGetDevice(&dev));
+        INIT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        c->simds = 4 * (int64_t)std::max(cus, 1);
+    }
     INIT_HIP(hipMalloc((void **)&c->workspace, elem * total));
     INIT_HIP(hipMalloc((void **)&c->d_partials, sizeof(fdm::StatsPartial) * fdm::kStatsBlocks));
     INIT_HIP(hipMalloc((void **)&c->d_stats, sizeof(double) * 5 * n_instances));
@@ -869,11 +896,7 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
             return fail(c, e == hipErrorOutOfMemory ? FDM_ERR_OUT_OF_MEMORY : FDM_ERR_DEVICE,
                         std::string("hipMalloc: ") + hipGetErrorString(e));
     }
-    // SIMDs of the device (four per compute unit), for the balanced heights
-    int dev = 0, cus = 0;
-    FDM_HIP(c, hipGetDevice(&dev));
-    FDM_HIP(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int64_t simds = 4 * (int64_t)std::max(cus, 1);
+    const int64_t simds = c->simds;
     std::vector<void *> s11(c->n), s12(c->n);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool was_batched = c->batched, was_fused = c->fused;

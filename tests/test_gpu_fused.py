@@ -170,6 +170,24 @@ def test_bands_field_4096_fused_equals_plain(fdm):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("n", [256, 2048, 4096])
+def test_fused_default_tile_height(fdm, n):
+    """Without a height asked for, a fused context tiles at the smallest
+    height with at most five waves (one per 56-column tile) per SIMD, or by
+    the unfused rule where that height is below 4 or above 64 rows; the
+    results do not depend on it (the bitwise tests above)."""
+    import torch
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    strips = -(-n // 56)
+    r = next(r for r in range(1, n + 1) if strips * -(-n // r) <= 5 * simds)
+    if not 4 <= r <= 64:   # the unfused rule: (strip, row) pairs / 6144, up to a multiple of 4, in [4, 16]
+        rows = -(-(-(-n // 60) * n) // 6144)
+        r = min(16, max(4, -(-rows // 4) * 4), n)
+    ctx = fdm.fdm_transport_init(fdm.desc(n, n, limiter="superbee", cfl=0.4, v0=-1.0), options=FUSED)
+    assert fdm.fdm_tile_rows(ctx, 0) == r
+    fdm.fdm_destroy(ctx)
+
+
 def _run_chunks(F, a11, a12, steps, chunk, options, **kw):
     import torch
     ny, nx = a11.shape
