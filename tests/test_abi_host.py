@@ -222,3 +222,10 @@ def test_fused_schedule_needs_fp32_two_stage_semidiscrete(fdm, kw, opts):
         fdm.fdm_transport_init(fdm.desc(16, 16, **kw), options=opts)
     assert e.value.status == fdm.FDM_ERR_INVALID_ARG
     assert "fused" in fdm.fdm_last_error(None)
+
+
+def test_missing_library_fails_loudly(fdm, monkeypatch, tmp_path):
+    """No fallback path: without libfdm.so the binding raises."""
+    monkeypatch.setattr(fdm, "_lib", None)
+    with pytest.raises(RuntimeError, match="not found"):
+        fdm.load_library(str(tmp_path / "libfdm.so"))
