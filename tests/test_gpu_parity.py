@@ -674,3 +674,31 @@ def test_extreme_aspect_ratios(fdm, oracle, nx, ny):
     _, fused = gpu_run(a11, a12, 4, options={"schedule": "fused"}, **kw)
     assert np.array_equal(plain[-1][1], fused[-1][1]) and np.array_equal(plain[-1][2], fused[-1][2])
     assert rel_l1(plain[-1][1], plain[-1][2], o11, o12, a11, a12) <= tolerance(4)
+
+
+@pytest.mark.parametrize("schedule", ["plain", "fused"])
+def test_over_4gib_arrays_tile_periodically(fdm, schedule):
+    """A 36000^2 grid, 5.2 GB per density array (row offsets beyond 32 bits),
+    made of 18 x 18 copies of a 2000^2 loop.  The scheme is local and the
+    same at every node, so after 3 steps every copy equals the 2000^2 run
+    bit for bit."""
+    import torch
+    t, m = 2000, 18
+    a11, a12 = W.ring(t, t, R=500.0, sigma=6.0)
+    kw = dict(limiter="superbee", cfl=0.4, v0=-1.0)
+    dt_small, small = gpu_run(a11, a12, 3, options={"schedule": schedule}, **kw)
+    s11 = torch.from_numpy(small[-1][1].astype(np.float32)).cuda()
+    s12 = torch.from_numpy(small[-1][2].astype(np.float32)).cuda()
+    n = t * m
+    b11 = to_dev(a11).repeat(m, m)
+    b12 = to_dev(a12).repeat(m, m)
+    ctx = fdm.fdm_transport_init(fdm.desc(n, n, **kw), options={"schedule": schedule})
+    assert fdm.fdm_transport_dt(ctx) == dt_small
+    fdm.fdm_transport_step(ctx, b11, b12, 3)
+    torch.cuda.synchronize()
+    fdm.fdm_destroy(ctx)
+    for big, ref in ((b11, s11), (b12, s12)):
+        same = torch.equal(big.view(m, t, m, t), ref.view(1, t, 1, t).expand(m, t, m, t))
+        assert same
+    del b11, b12
+    torch.cuda.empty_cache()
