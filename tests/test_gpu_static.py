@@ -98,3 +98,24 @@ def test_mean_is_the_macroscopic_stress_and_densities_untouched(fdm, precision):
     assert np.array_equal(t11.cpu().numpy(), a11.astype(dt)) and np.array_equal(t12.cpu().numpy(), a12.astype(dt))
     sbar = 2 * 1.0 * 0.002 - 1.0 * 0.05 * 3 / 96
     assert abs(g.mean() - sbar) < (1e-13 if precision == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("nx,ny", [(4096, 2048), (1009, 503), (2048, 3)])
+def test_large_and_prime_sizes(fdm, precision, nx, ny):
+    """FFT lengths beyond one pass (4096 x 2048), prime lengths (1009 x 503)
+    and a thin strip (2048 x 3), on a thin cell (L3 = 16 voxels, h = 4) so
+    the oracle's sum over the x3 modes stays short; same bars as above."""
+    rng = np.random.default_rng(nx + ny)
+    x = np.arange(nx)[None, :] / nx
+    y = np.arange(ny)[:, None] / ny
+    phi = 0.2 * np.sin(2 * np.pi * (5 * x + 2 * y)) + 0.05 * rng.normal(size=(ny, nx))
+    a11, a12 = W.densities_from_phi(phi)
+    kw = dict(layer_h=4.0, cell_l3=16.0, eps13=0.002, phi_mean=float(phi.mean()))
+    g, _ = _solve(fdm, a11, a12, precision, **kw)
+    o = _oracle(a11, a12, **kw)
+    l2, linf = _errors(g, o)
+    if precision == "fp64":
+        assert l2 < 1e-12 and linf < 1e-12, (l2, linf)
+    else:
+        assert l2 < 1e-5 and linf < 1e-4, (l2, linf)
