@@ -696,9 +696,18 @@ def test_over_4gib_arrays_tile_periodically(fdm, schedule):
     assert fdm.fdm_transport_dt(ctx) == dt_small
     fdm.fdm_transport_step(ctx, b11, b12, 3)
     torch.cuda.synchronize()
+    big_stats = fdm.fdm_transport_stats(ctx, b11, b12)[0]
     fdm.fdm_destroy(ctx)
     for big, ref in ((b11, s11), (b12, s12)):
         same = torch.equal(big.view(m, t, m, t), ref.view(1, t, 1, t).expand(m, t, m, t))
         assert same
+    # the diagnostics over 1.3e9 nodes: compensated sums of m^2 equal copies
+    ctx = fdm.fdm_transport_init(fdm.desc(t, t, **kw))
+    small_stats = fdm.fdm_transport_stats(ctx, s11, s12)[0]
+    fdm.fdm_destroy(ctx)
+    assert big_stats["max_norm"] == small_stats["max_norm"] and big_stats["nonfinite"] == 0
+    assert big_stats["sum_abs"] == pytest.approx(m * m * small_stats["sum_abs"], rel=1e-13)
+    for k in ("sum11", "sum12"):
+        assert abs(big_stats[k] - m * m * small_stats[k]) <= 1e-13 * big_stats["sum_abs"]
     del b11, b12
     torch.cuda.empty_cache()
