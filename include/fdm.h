@@ -52,7 +52,7 @@ typedef enum fdm_status {
     FDM_ERR_INVALID_ARG = 1,   /* a descriptor field or pointer is invalid        */
     FDM_ERR_DEVICE = 2,        /* a HIP call failed (sticky, see fdm_last_error)  */
     FDM_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed                     */
-    FDM_ERR_CFL = 4,           /* a fixed dt exceeds the Courant-number-1 bound   */
+    FDM_ERR_CFL = 4,           /* the step exceeds the stability bound (below)    */
     FDM_ERR_NONFINITE = 5,     /* a NaN or Inf was found in the densities         */
     FDM_ERR_UNSUPPORTED = 6    /* feature not available                           */
 } fdm_status;
@@ -108,11 +108,12 @@ typedef struct fdm_transport_desc {
                                 midpoint (u + dt L(u + dt/2 L(u)), the
                                 midpoint rule of sec. 3.2.2).  The fully
                                 discrete scheme takes 0 or 1 (one pass)          */
-    double cfl;              /* Courant number nu in (0, 1] used when dt == 0   */
+    double cfl;              /* Courant number nu in (0, 1] used when dt == 0
+                                (sec. 4.3: |v0| dt / dx); see the bound below   */
     double dt;               /* 0: dt = nu min(dx,dy) / s_max rounded down to a
                                 float; > 0: this step (rounded to the nearest
-                                float), rejected with FDM_ERR_CFL if
-                                dt s_max / min(dx,dy) > 1                        */
+                                float).  Either way the step must satisfy the
+                                stability bound below, else FDM_ERR_CFL        */
     int32_t velocity;        /* fdm_velocity                                    */
     double v0;               /* LAW: uniform celerity when v0_field is NULL,
                                 rounded to float (the kernels' and s_max's)     */
@@ -121,6 +122,23 @@ typedef struct fdm_transport_desc {
     double V[2];             /* PRESCRIBED: velocity (V1, V2), rounded to
                                 float; s_max = max(|V1|/dx, |V2|/dy) min(dx,dy)  */
 } fdm_transport_desc;
+
+/* Stability bound.  nu2 = dt (S1/dx + S2/dy), the sum of the Courant numbers
+ * along x and y, with S1, S2 bounds on |dH/dp1|, |dH/dp2| (LAW: max |v0| for
+ * both, since |p_i| <= |p|; PRESCRIBED: |V1|, |V2|) and an axis of a single
+ * node contributing 0.  fdm_transport_init rejects a descriptor with
+ * FDM_ERR_CFL when
+ *   nu2 > 1    (any scheme: the first-order upwind stage is unstable in 2-D
+ *               beyond it), or
+ *   nu2 > 1/2  for one forward-Euler stage with a limiter (time_order 1, or
+ *               the fully discrete scheme): a limited Euler step grows
+ *               beyond it with the compressive limiters.
+ * For LAW with dt == 0 the check uses the cfl alone (dt max|v0| <=
+ * cfl min(dx,dy) whatever the celerity), so on a square grid the
+ * two-stage schemes take cfl <= 0.5 and a limited Euler stage cfl <= 0.25,
+ * the paper's value; a 1-D problem (ny == 1) takes twice that.  With a
+ * fixed dt over a celerity field the bound is checked after the device
+ * reduction of max |v0|, otherwise before any HIP call. */
 
 /* Scheduling options; pass NULL for the defaults. */
 typedef enum fdm_schedule {

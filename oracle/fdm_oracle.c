@@ -223,13 +223,38 @@ static inline int64_t wrap(int64_t i, int64_t n)
     return i < 0 ? i + n : i;
 }
 
-/* Numerical Hamiltonian at every node (Steps 1-4). hhat has nx*ny entries. */
-void orc_hhat_field(const orc_problem *P, const double *a11, const double *a12,
-                    double *hhat)
+/* Work arrays of nx*ny values each, allocated once per run. */
+typedef struct {
+    double *sx, *sy, *h, *r11, *r12, *u11, *u12;
+} orc_work;
+
+static int work_alloc(orc_work *w, int64_t n)
+{
+    double **f[] = {&w->sx, &w->sy, &w->h, &w->r11, &w->r12, &w->u11, &w->u12};
+    int ok = 1;
+    for (size_t i = 0; i < sizeof(f) / sizeof(f[0]); ++i) {
+        *f[i] = (double *)malloc(sizeof(double) * (size_t)n);
+        ok &= *f[i] != NULL;
+    }
+    return ok;
+}
+
+static void work_free(orc_work *w)
+{
+    free(w->sx);
+    free(w->sy);
+    free(w->h);
+    free(w->r11);
+    free(w->r12);
+    free(w->u11);
+    free(w->u12);
+}
+
+/* Numerical Hamiltonian at every node (Steps 1-4); sx, sy hold the slopes. */
+static void hhat_field_w(const orc_problem *P, const double *a11, const double *a12,
+                         double *hhat, double *sx, double *sy)
 {
     const int64_t nx = P->nx, ny = P->ny;
-    double *sx = (double *)malloc(sizeof(double) * nx * ny);
-    double *sy = (double *)malloc(sizeof(double) * nx * ny);
 
     /* Step 1: limited slopes of w_x = alpha_12 along x and of
      * w_y = -alpha_11 along y, one per edge. */
@@ -263,18 +288,28 @@ void orc_hhat_field(const orc_problem *P, const double *a11, const double *a12,
             hhat[k * nx + j] = orc_hhat_node(P, v0, pxm, pxp, pym, pyp);
         }
     }
+}
+
+/* Numerical Hamiltonian at every node (Steps 1-4). hhat has nx*ny entries. */
+void orc_hhat_field(const orc_problem *P, const double *a11, const double *a12,
+                    double *hhat)
+{
+    const int64_t n = P->nx * P->ny;
+    double *sx = (double *)malloc(sizeof(double) * n);
+    double *sy = (double *)malloc(sizeof(double) * n);
+    hhat_field_w(P, a11, a12, hhat, sx, sy);
     free(sx);
     free(sy);
 }
 
 /* Rate of the density components: d(alpha_12)/dt = -d1 Hhat and
  * d(alpha_11)/dt = +d2 Hhat, differenced across each edge (eq. 57). */
-void orc_stage_rate(const orc_problem *P, const double *a11, const double *a12,
-                    double *r11, double *r12)
+static void stage_rate_w(const orc_problem *P, const double *a11, const double *a12,
+                         double *r11, double *r12, orc_work *w)
 {
     const int64_t nx = P->nx, ny = P->ny;
-    double *h = (double *)malloc(sizeof(double) * nx * ny);
-    orc_hhat_field(P, a11, a12, h);
+    double *h = w->h;
+    hhat_field_w(P, a11, a12, h, w->sx, w->sy);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < ny; ++k) {
         for (int64_t j = 0; j < nx; ++j) {
@@ -285,7 +320,15 @@ void orc_stage_rate(const orc_problem *P, const double *a11, const double *a12,
             r11[k * nx + j] = (hyp - h0) / P->dy;
         }
     }
-    free(h);
+}
+
+void orc_stage_rate(const orc_problem *P, const double *a11, const double *a12,
+                    double *r11, double *r12)
+{
+    orc_work w;
+    work_alloc(&w, P->nx * P->ny);
+    stage_rate_w(P, a11, a12, r11, r12, &w);
+    work_free(&w);
 }
 
 /* ------------------------------------------- fully discrete scheme (3.2.3) */
@@ -379,12 +422,11 @@ double orc_fd_increment_node(const orc_problem *P, double v0,
 }
 
 /* Node increments phi^{n+1} - phi^n of the fully discrete scheme at every
- * node (Steps 1-4); inc has nx*ny entries. */
-void orc_fd_increment_field(const orc_problem *P, const double *a11, const double *a12, double *inc)
+ * node (Steps 1-4); sx, sy hold the slopes. */
+static void fd_increment_field_w(const orc_problem *P, const double *a11, const double *a12, double *inc,
+                                 double *sx, double *sy)
 {
     const int64_t nx = P->nx, ny = P->ny;
-    double *sx = (double *)malloc(sizeof(double) * nx * ny);
-    double *sy = (double *)malloc(sizeof(double) * nx * ny);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < ny; ++k) {
         for (int64_t j = 0; j < nx; ++j) {
@@ -404,6 +446,16 @@ void orc_fd_increment_field(const orc_problem *P, const double *a11, const doubl
                                                     -a11[f_down], sy[f_down], -a11[f_up], sy[f_up]);
         }
     }
+}
+
+/* Node increments phi^{n+1} - phi^n of the fully discrete scheme at every
+ * node (Steps 1-4); inc has nx*ny entries. */
+void orc_fd_increment_field(const orc_problem *P, const double *a11, const double *a12, double *inc)
+{
+    const int64_t n = P->nx * P->ny;
+    double *sx = (double *)malloc(sizeof(double) * n);
+    double *sy = (double *)malloc(sizeof(double) * n);
+    fd_increment_field_w(P, a11, a12, inc, sx, sy);
     free(sx);
     free(sy);
 }
@@ -411,11 +463,11 @@ void orc_fd_increment_field(const orc_problem *P, const double *a11, const doubl
 /* One fully discrete step in place: w_x(j+1/2) += (inc_{j+1} - inc_j)/dx and
  * w_y(k+1/2) += (inc_{k+1} - inc_k)/dy, i.e. the new densities are the
  * differences of phi^{n+1}. */
-static void fd_step(const orc_problem *P, double *a11, double *a12)
+static void fd_step(const orc_problem *P, double *a11, double *a12, orc_work *w)
 {
     const int64_t nx = P->nx, ny = P->ny;
-    double *inc = (double *)malloc(sizeof(double) * nx * ny);
-    orc_fd_increment_field(P, a11, a12, inc);
+    double *inc = w->h;
+    fd_increment_field_w(P, a11, a12, inc, w->sx, w->sy);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < ny; ++k) {
         for (int64_t j = 0; j < nx; ++j) {
@@ -426,67 +478,74 @@ static void fd_step(const orc_problem *P, double *a11, double *a12)
             a11[k * nx + j] = a11[k * nx + j] - (dyp - d0) / P->dy;
         }
     }
-    free(inc);
 }
 
-/* One time step in place. */
-void orc_step(const orc_problem *P, double *a11, double *a12)
+/* One time step in place (w: work arrays of nx*ny values). */
+static void step_w(const orc_problem *P, double *a11, double *a12, orc_work *w)
 {
     if (P->scheme == ORC_FULLY_DISCRETE) {
-        fd_step(P, a11, a12);
+        fd_step(P, a11, a12, w);
         return;
     }
     const int64_t n = P->nx * P->ny;
     const double dt = P->dt;
-    double *r11 = (double *)malloc(sizeof(double) * n);
-    double *r12 = (double *)malloc(sizeof(double) * n);
-    orc_stage_rate(P, a11, a12, r11, r12);
+    double *r11 = w->r11, *r12 = w->r12;
+    stage_rate_w(P, a11, a12, r11, r12, w);
     if (P->time_order == 1) {
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             a11[i] = a11[i] + dt * r11[i];
             a12[i] = a12[i] + dt * r12[i];
         }
     } else if (P->time_order == 3) {
         /* explicit midpoint: u1 = u + (dt/2) L(u);  u_new = u + dt L(u1). */
-        double *u11 = (double *)malloc(sizeof(double) * n);
-        double *u12 = (double *)malloc(sizeof(double) * n);
+        double *u11 = w->u11, *u12 = w->u12;
         const double hdt = 0.5 * dt;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             u11[i] = a11[i] + hdt * r11[i];
             u12[i] = a12[i] + hdt * r12[i];
         }
-        orc_stage_rate(P, u11, u12, r11, r12);
+        stage_rate_w(P, u11, u12, r11, r12, w);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             a11[i] = a11[i] + dt * r11[i];
             a12[i] = a12[i] + dt * r12[i];
         }
-        free(u11);
-        free(u12);
     } else {
         /* Heun: u1 = u + dt L(u);  u_new = u/2 + (u1 + dt L(u1))/2. */
-        double *u11 = (double *)malloc(sizeof(double) * n);
-        double *u12 = (double *)malloc(sizeof(double) * n);
+        double *u11 = w->u11, *u12 = w->u12;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             u11[i] = a11[i] + dt * r11[i];
             u12[i] = a12[i] + dt * r12[i];
         }
-        orc_stage_rate(P, u11, u12, r11, r12);
+        stage_rate_w(P, u11, u12, r11, r12, w);
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) {
             a11[i] = 0.5 * a11[i] + 0.5 * (u11[i] + dt * r11[i]);
             a12[i] = 0.5 * a12[i] + 0.5 * (u12[i] + dt * r12[i]);
         }
-        free(u11);
-        free(u12);
     }
-    free(r11);
-    free(r12);
 }
 
-/* n_steps time steps in place. */
+/* One time step in place. */
+void orc_step(const orc_problem *P, double *a11, double *a12)
+{
+    orc_work w;
+    work_alloc(&w, P->nx * P->ny);
+    step_w(P, a11, a12, &w);
+    work_free(&w);
+}
+
+/* n_steps time steps in place (the work arrays are allocated once). */
 void orc_run(const orc_problem *P, double *a11, double *a12, int64_t n_steps)
 {
+    orc_work w;
+    work_alloc(&w, P->nx * P->ny);
     for (int64_t s = 0; s < n_steps; ++s)
-        orc_step(P, a11, a12);
+        step_w(P, a11, a12, &w);
+    work_free(&w);
 }
 
 /* ---------------------------------------------------------------- Time step */

@@ -1,10 +1,13 @@
 """Build ``libfdm.so`` (the HIP library behind include/fdm.h) for gfx950.
 
 Run ``python -m paper_1911_03225_amd.build`` (or ``__graft_entry__.build()``).
-The library is written next to this file so it travels with the source tree.
+Each source is compiled to an object in parallel (``_build/`` under the
+package), then linked; the library is written next to this file so it
+travels with the source tree.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import shutil
 import subprocess
@@ -13,8 +16,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdm.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
-           ("fdm_kernels.hip", "fdm_stage_f32.hip", "fdm_stage_f64.hip", "fdm_static.hip", "fdm_api.hip")]
+           ("fdm_kernels.hip", "fdm_stage_f32.hip", "fdm_stage_f64.hip", "fdm_static.hip", "fdm_api.hip",
+)]
 # rocFFT for the static solve's transforms
 LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = "gfx950"
@@ -29,7 +34,7 @@ def hipcc() -> str:
 
 def flags():
     return [
-        "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
+        "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
         "-mcode-object-version=5",
         # no packed FP32 (v_pk_*_f32) in device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,15 +43,35 @@ def flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + SOURCES + LIBS + ["-o", tmp]
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+    tmp = obj + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + flags() + ["-c", src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libfdm.so")
+        raise RuntimeError("hipcc failed on %s" % os.path.basename(src))
+    if r.stderr.strip() and verbose:
+        sys.stderr.write(r.stderr)
+    os.replace(tmp, obj)
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + objs + LIBS + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed linking libfdm.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -130,6 +130,65 @@ std::string check_desc(const fdm_transport_desc &d)
     return "";
 }
 
+// Largest float not above x (x > 0).
+float round_down_float(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, 0.0f);
+    return f;
+}
+
+// Stability bound of the step.  nu2 = dt (S1/dx + S2/dy) is the sum of the
+// per-axis Courant numbers, S_i a bound on |dH/dp_i| over the grid (LAW:
+// max |v0| on both axes, since |p_i| <= |p|; PRESCRIBED: |V_i|); an axis of
+// one node has no differences along it and adds nothing.  Beyond nu2 = 1 the
+// first-order upwind stage no longer writes each new value as a convex
+// combination of old ones and is unstable in 2-D.  One forward-Euler stage
+// with a limiter (time_order 1, or the fully discrete scheme) is held to
+// nu2 <= 1/2, the bound of a limited (MUSCL) forward-Euler step; the paper's
+// runs (Courant number 0.25 per axis, sec. 4.3-4.4) sit at exactly 1/2.
+double courant_sum(const fdm_transport_desc &d, double dt, double smax_law)
+{
+    const double ax = d.nx > 1 ? 1.0 : 0.0, ay = d.ny > 1 ? 1.0 : 0.0;
+    double s1 = smax_law, s2 = smax_law;
+    if (d.velocity == FDM_VELOCITY_PRESCRIBED) {
+        s1 = std::fabs((double)(float)d.V[0]);
+        s2 = std::fabs((double)(float)d.V[1]);
+    }
+    return dt * (s1 / d.dx * ax + s2 / d.dy * ay);
+}
+
+double courant_limit(const fdm_transport_desc &d, int32_t order)
+{
+    return (order == 1 && d.limiter != FDM_LIMITER_NONE) ? 0.5 : 1.0;
+}
+
+// nu2 of the step a descriptor implies: a fixed dt with the given max |v0|
+// (LAW), or the CFL-controlled step, for which dt max|v0| <= cfl min(dx, dy)
+// whatever the celerity (LAW) and dt follows from V (PRESCRIBED).
+double step_courant(const fdm_transport_desc &d, double smax_law)
+{
+    const double h = std::min(d.dx, d.dy);
+    if (d.dt > 0.0) return courant_sum(d, (double)(float)d.dt, smax_law);
+    if (d.velocity == FDM_VELOCITY_LAW) return courant_sum(d, d.cfl * h, 1.0);
+    const double smax =
+        std::max(std::fabs((double)(float)d.V[0]) / d.dx, std::fabs((double)(float)d.V[1]) / d.dy) * h;
+    return courant_sum(d, (double)round_down_float(smax > 0.0 ? d.cfl * h / smax : d.cfl * h), 0.0);
+}
+
+// "" if the step is within the bound, else the reason.
+std::string check_courant(const fdm_transport_desc &d, int32_t order, double smax_law)
+{
+    const double nu2 = step_courant(d, smax_law), lim = courant_limit(d, order);
+    if (nu2 <= lim * (1.0 + 1e-12)) return "";
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "dt (S1/dx + S2/dy) = %.6g exceeds %.3g (%s); lower %s", nu2, lim,
+                  lim < 1.0 ? "one forward-Euler stage with a limiter" : "the 2-D Courant bound",
+                  d.dt > 0.0 ? "dt" : "cfl");
+    return buf;
+}
+
 // A whole number of voxels: v / d within 1e-9 of an integer >= 1.
 bool whole_voxels(double v, double d, int *out)
 {
@@ -164,14 +223,6 @@ std::string check_static(const fdm_static_desc &d, fdm::StaticParams *q)
 double static_mean_stress(const fdm_static_desc &d, const fdm::StaticParams &q)
 {
     return 2.0 * d.mu * d.eps13 - d.mu * d.phi_mean * (double)q.h / (double)q.n3;
-}
-
-// Largest float not above x (x > 0).
-float round_down_float(double x)
-{
-    float f = (float)x;
-    if ((double)f > x) f = std::nextafter(f, 0.0f);
-    return f;
 }
 
 // Rows per wave tile.  Each tile recomputes one extra row of Hhat and
@@ -621,8 +672,15 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
           descs[0].scheme == FDM_SCHEME_SEMIDISCRETE))
         return fail(nullptr, FDM_ERR_INVALID_ARG,
                     "the fused schedule needs FP32 precision, time_order 2 or 3 and the semi-discrete scheme");
-    // Courant bound of a fixed dt needs s_max; uniform cases are checked here,
-    // field cases after the device reduction below.
+    // Stability bound of the step: every case but a fixed dt over a celerity
+    // field is decided here, before any HIP call; that one needs the field's
+    // max |v0| (after the device reduction below).
+    for (int i = 0; i < n_instances; ++i) {
+        const fdm_transport_desc &d = descs[i];
+        if (d.velocity == FDM_VELOCITY_LAW && d.v0_field && d.dt > 0.0) continue;
+        const std::string m = check_courant(d, order, std::fabs((double)(float)d.v0));
+        if (!m.empty()) return fail(nullptr, FDM_ERR_CFL, "descriptor " + std::to_string(i) + ": " + m);
+    }
     fdm_ctx *c = new (std::nothrow) fdm_ctx;
     if (!c) return fail(nullptr, FDM_ERR_OUT_OF_MEMORY, "host allocation failed");
     c->stream = (hipStream_t)hip_stream;
@@ -701,9 +759,12 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
         float dt;
         if (d.dt > 0.0) {
             dt = (float)d.dt;
-            if ((double)dt * smax / h > 1.0) {
-                fail(c, FDM_ERR_CFL, "dt of descriptor " + std::to_string(i) + " exceeds the Courant-number-1 bound");
-                return bail(FDM_ERR_CFL);
+            if (d.velocity == FDM_VELOCITY_LAW && d.v0_field) {
+                const std::string m = check_courant(d, order, smax);
+                if (!m.empty()) {
+                    fail(c, FDM_ERR_CFL, "descriptor " + std::to_string(i) + ": " + m);
+                    return bail(FDM_ERR_CFL);
+                }
             }
         } else {
             dt = round_down_float(smax > 0.0 ? d.cfl * h / smax : d.cfl * h);
@@ -1025,7 +1086,7 @@ const char *fdm_status_string(fdm_status s)
     case FDM_ERR_INVALID_ARG: return "invalid argument";
     case FDM_ERR_DEVICE: return "HIP device error";
     case FDM_ERR_OUT_OF_MEMORY: return "out of device memory";
-    case FDM_ERR_CFL: return "time step above the Courant-number-1 bound";
+    case FDM_ERR_CFL: return "time step above the stability bound";
     case FDM_ERR_NONFINITE: return "non-finite densities";
     case FDM_ERR_UNSUPPORTED: return "unsupported";
     }

@@ -127,6 +127,61 @@ def test_invalid_descriptor_rejected_on_host(fdm, kw, msg):
     assert msg in fdm.fdm_last_error(None)
 
 
+# The stability bound nu2 = dt (S1/dx + S2/dy) <= 1 (1/2 for one limited
+# forward-Euler stage), decided on the host for every case but a fixed dt
+# over a celerity field.
+COURANT_BAD = [
+    (dict(cfl=0.6), "2-D Courant"),                                   # LAW, Heun, square grid: nu2 = 1.2
+    (dict(cfl=0.8, dx=0.5), "2-D Courant"),                           # nu2 = 0.8 * 0.5 * (1/0.5 + 1/1) = 1.2
+    (dict(cfl=0.26, time_order=1), "forward-Euler"),                  # limited Euler stage: nu2 = 0.52
+    (dict(cfl=0.3, time_order=1, scheme="fully_discrete"), "forward-Euler"),
+    (dict(limiter="none", time_order=1, velocity="prescribed", V=(1.0, 0.5), cfl=1.0), "2-D Courant"),
+    (dict(dt=0.6, v0=-1.0), "2-D Courant"),                           # fixed dt, uniform celerity
+    (dict(dt=0.3, v0=-1.0, time_order=1, limiter="superbee"), "forward-Euler"),
+    (dict(dt=0.6, velocity="prescribed", V=(0.9, 0.9)), "2-D Courant"),
+    (dict(nx=1, ny=64, cfl=1.0, time_order=1), "forward-Euler"),      # 1-D along y
+]
+
+
+@pytest.mark.parametrize("kw,msg", COURANT_BAD)
+def test_courant_bound_rejected_on_host(fdm, kw, msg):
+    args = dict(nx=16, ny=16)
+    args.update(kw)
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init(fdm.desc(**args))
+    assert e.value.status == fdm.FDM_ERR_CFL
+    assert msg in fdm.fdm_last_error(None)
+
+
+COURANT_OK = [
+    dict(cfl=0.5),                                                    # nu2 = 1: the colliding-pulse runs
+    dict(cfl=0.25, time_order=1),                                     # the paper's Courant number
+    dict(cfl=0.25, time_order=1, scheme="fully_discrete"),
+    dict(ny=1, cfl=1.0),                                              # 1-D: one axis
+    dict(ny=1, cfl=0.5, time_order=1, limiter="superbee"),
+    dict(ny=1, limiter="none", time_order=1, velocity="prescribed", V=(1.0, 0.5), cfl=1.0),
+    dict(limiter="none", time_order=1, velocity="prescribed", V=(1.0, 0.0), dt=1.0),
+    dict(limiter="none", time_order=1, cfl=0.5),
+    dict(dt=0.5, v0=-1.0),
+    dict(dt=1.0, v0=-1.0, dx=2.0, dy=2.0),
+    dict(velocity="prescribed", V=(0.7, -0.4), dx=1.3, dy=0.6, cfl=0.5),
+]
+
+
+@pytest.mark.parametrize("kw", COURANT_OK)
+def test_courant_bound_accepts_stable_steps(fdm, kw):
+    """Within the bound the descriptor passes the host checks (and, with no
+    GPU, fails only at the first HIP call)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    args = dict(nx=16, ny=16)
+    args.update(kw)
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init(fdm.desc(**args))
+    assert e.value.status == fdm.FDM_ERR_DEVICE, fdm.fdm_last_error(None)
+
+
 def test_mixed_schemes_rejected(fdm):
     with pytest.raises(fdm.FdmError) as e:
         fdm.fdm_transport_init([fdm.desc(8, 8, time_order=1),

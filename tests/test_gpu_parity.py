@@ -43,11 +43,17 @@ def test_colliding_pulses(fdm, oracle, limiter):
     assert not np.any(g[0])                      # alpha_11 stays exactly 0
 
 
-def test_exact_period(fdm, oracle):
-    """First order, one stage, Courant 1, V = (1, 0.5): exact return after 64 steps."""
+@pytest.mark.parametrize("ny,V", [(1, (1.0, 0.5)), (64, (1.0, 0.0))])
+def test_exact_period(fdm, oracle, ny, V):
+    """First order, one stage, Courant number 1 along x on x-only data:
+    exact return after 64 steps.  The run is explicitly one-dimensional: a
+    single row with V = (1, 0.5) (the y axis has no differences), or the
+    64 x 64 grid with V = (1, 0).  V = (1, 0.5) on the 64 x 64 grid at
+    dt = 1 is rejected (2-D Courant number 1.5, unstable for general data)."""
     a11, a12 = W.exact_period_profile(64)
+    a11, a12 = np.ascontiguousarray(a11[:ny]), np.ascontiguousarray(a12[:ny])
     dt, rep, g, o = compare_run(oracle, a11, a12, 64, every=16, limiter="none", time_order=1,
-                                velocity="prescribed", V=(1.0, 0.5), cfl=1.0)
+                                velocity="prescribed", V=V, cfl=1.0)
     assert dt == 1.0
     _assert_report(rep, 64)
     assert np.max(np.abs(g[1] - a12)) <= 1e-6 * np.max(np.abs(a12))
@@ -437,10 +443,19 @@ def test_run_history(fdm, oracle):
 def test_error_paths(fdm):
     from paper_1911_03225_amd import fdm as F
     a11, a12 = W.ring(64, 64, R=16.0, sigma=2.0)
-    # a fixed dt above the Courant-number-1 bound
+    # a fixed dt above the stability bound
     with pytest.raises(F.FdmError) as e:
         F.fdm_transport_init(F.desc(64, 64, v0=-2.0, dt=0.6))
     assert e.value.status == F.FDM_ERR_CFL
+    # ... over a celerity field: checked after the device reduction of max |v0|
+    field = to_dev(np.full((64, 64), 0.5, np.float32))
+    F.fdm_destroy(F.fdm_transport_init(F.desc(64, 64, v0_field=field, dt=1.0)))     # nu2 = 1
+    with pytest.raises(F.FdmError) as e:
+        F.fdm_transport_init(F.desc(64, 64, v0_field=field, dt=1.01))
+    assert e.value.status == F.FDM_ERR_CFL and "2-D Courant" in F.fdm_last_error(None)
+    with pytest.raises(F.FdmError) as e:
+        F.fdm_transport_init(F.desc(64, 64, v0_field=field, dt=0.6, time_order=1))
+    assert e.value.status == F.FDM_ERR_CFL and "forward-Euler" in F.fdm_last_error(None)
     # a non-finite celerity field
     bad = np.ones((64, 64), np.float32)
     bad[3, 5] = np.nan
@@ -529,7 +544,7 @@ def _bitwise_cases():
     cases.append(("bands-field", a11, a12, dict(limiter="theta", theta=1.5, cfl=0.45, v0_field=v0), 80))
     a11, a12 = W.ring(61, 67, R=12.0, sigma=3.0)
     cases.append(("euler-prescribed", a11, a12, dict(limiter="superbee", time_order=1, velocity="prescribed",
-                                                     V=(0.7, -0.4), cfl=0.5), 31))
+                                                     V=(0.7, -0.4), cfl=0.3), 31))
     a11, a12 = W.ring(110, 90, R=20.0, sigma=2.5)
     cases.append(("midpoint-ring", a11, a12, dict(limiter="superbee", time_order=3, cfl=0.4, v0=-1.0), 70))
     rng = np.random.default_rng(4)
@@ -618,7 +633,8 @@ STEP_CASES = [
     dict(nx=32, ny=24, dx=0.7, dy=1.9, cfl=0.45, v0=2.3),
     dict(nx=40, ny=16, dx=1.3, dy=0.6, cfl=0.5, velocity="prescribed", V=(0.7, -0.4)),
     dict(nx=40, ny=16, dx=1.3, dy=0.6, cfl=0.3, velocity="prescribed", V=(-0.2, 0.9)),
-    dict(nx=40, ny=16, dx=0.9, dy=0.9, cfl=1.0, velocity="prescribed", V=(1.0, 0.5)),
+    dict(nx=40, ny=16, dx=0.9, dy=0.9, cfl=0.6, velocity="prescribed", V=(1.0, 0.5)),
+    dict(nx=40, ny=1, dx=0.9, dy=0.9, cfl=1.0, velocity="prescribed", V=(1.0, 0.5)),
     dict(nx=64, ny=48, dx=1.1, dy=0.8, cfl=0.45, field=True),
     dict(nx=8, ny=8, dx=1.0, dy=1.0, cfl=0.4, v0=0.0),
 ]
