@@ -220,17 +220,30 @@ fdm_status fdm_transport_init(const fdm_transport_desc *descs, int32_t n_instanc
                               const fdm_options *options, void *hip_stream,
                               fdm_ctx **out);
 
-/* Enqueue n_steps >= 0 time steps of every instance.  alpha11[i], alpha12[i]
- * are the device arrays of instance i (see layout above; float, or double
- * with FDM_PRECISION_FP64); they are read and written in place.
- * Asynchronous: returns after enqueueing. */
+/* Enqueue n_steps >= 0 time steps of every instance.  One step is the
+ * evolution problem of the layer case (sec. 3.2.3, the 2-D form of the
+ * sec. 3.2.2 scheme): at every node Step 1 limited slopes (eq. 43-44),
+ * Step 2 one-sided derivatives (eq. 46) and speeds (eq. 53), Steps 3-4 the
+ * numerical Hamiltonian (eq. 54-55 with the dt -> 0 limit, or at finite dt
+ * for FULLY_DISCRETE), then the conservative update of the two density
+ * components (the alpha form, eq. 57), once per stage of time_order.
+ * alpha11[i], alpha12[i] are the device arrays of instance i (see layout
+ * above; float, or double with FDM_PRECISION_FP64); they are read and
+ * written in place.  The arrays are passed as void* because their element
+ * type follows the context's precision.  Asynchronous: returns after
+ * enqueueing. */
 fdm_status fdm_transport_step(fdm_ctx *ctx, void *const *alpha11,
                               void *const *alpha12, int32_t n_steps);
 
-/* Diagnostics of every instance's current state into out[0..n_instances-1]
- * (sums, norms, non-finite count; see fdm_stats).  Synchronizes the stream.
- * Returns FDM_ERR_NONFINITE (after filling out) if any instance holds a NaN
- * or Inf. */
+/* Diagnostics of every instance's current state into out[0..n_instances-1]:
+ * the summed densities, which the alpha form conserves (the Burgers vector,
+ * sec. 2.1; eq. 2 keeps div alpha = 0), their drift since the first stats
+ * call, the total |alpha| (the annihilation of sec. 4.3 lowers it), the
+ * largest |alpha| (whose transport sec. 4.4 discusses, eq. 62) and the
+ * non-finite count; see fdm_stats.  The context does not keep array
+ * pointers between calls, so the arrays to measure are passed here (as in
+ * fdm_transport_step).  Synchronizes the stream.  Returns
+ * FDM_ERR_NONFINITE (after filling out) if any instance holds a NaN or Inf. */
 fdm_status fdm_transport_stats(fdm_ctx *ctx, void *const *alpha11,
                                void *const *alpha12, fdm_stats *out);
 

@@ -36,6 +36,8 @@ input.  Frequencies are the continuous ones of the discrete Fourier modes,
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 
@@ -73,8 +75,11 @@ def chi_hat_sq(n3: int, h: int) -> np.ndarray:
     return np.abs(np.fft.fft(chi) / n3) ** 2
 
 
+@functools.lru_cache(maxsize=16)
 def layer_multiplier(nx: int, ny: int, dx: float, dy: float, nu: float, h: int, n3: int) -> np.ndarray:
-    """K[m2, m1] of tau13^ = -mu K phi^ (m != 0); K[0, 0] = 0."""
+    """K[m2, m1] of tau13^ = -mu K phi^ (m != 0); K[0, 0] = 0.  A pure
+    function of the cell, so it is computed once per cell and kept
+    (read-only) for the steps of a coupled run."""
     x1, x2, x3 = _xi(nx, dx), _xi(ny, dy), _xi(n3, dx)
     c2 = chi_hat_sq(n3, h)
     K = np.zeros((ny, nx))
@@ -88,6 +93,7 @@ def layer_multiplier(nx: int, ny: int, dx: float, dy: float, nu: float, h: int, 
         K += c2[m3] * G
     K *= n3 / h
     K[0, 0] = 0.0
+    K.setflags(write=False)
     return K
 
 

@@ -113,14 +113,30 @@ template <> struct Arith<double> {
 
 // ---------------------------------------------------------------- Step 1
 
-// Limiter kinds compiled separately: the minmod family shares one body with
-// a runtime theta (1 for minmod, 2 for MC), so every launch form runs the
-// same instructions for a given limiter.
-enum : int { LK_NONE = 0, LK_THETA = 1, LK_SUPERBEE = 2 };
+// Limiter kinds compiled separately.  The minmod family shares one body with
+// a runtime theta (2 for MC, or a given theta), so every launch form runs the
+// same instructions for a given limiter.  Minmod itself (theta = 1) has its
+// own float body: there the centred argument (D+ + D-)/2 always lies between
+// D+ and D-, so the three-argument minmod is the two-argument minmod(D-, D+).
+// The float64 arithmetic keeps the definition's three arguments (bit for bit
+// with the oracle), so there minmod stays a theta kind.
+enum : int { LK_NONE = 0, LK_THETA = 1, LK_SUPERBEE = 2, LK_MINMOD = 3 };
 
-__host__ __device__ constexpr int limiter_kind(int lim)
+template <int K> struct LimTag {
+    static constexpr int value = K;
+};
+
+// f(LimTag<kind>{}) for a limiter code (the public enum), one instantiation
+// per kind; F32: float arithmetic, where minmod is a kind of its own.
+template <bool F32, typename F>
+__host__ __device__ __forceinline__ decltype(auto) with_limiter(int lim, F &&f)
 {
-    return lim == LIM_NONE ? LK_NONE : (lim == LIM_SUPERBEE ? LK_SUPERBEE : LK_THETA);
+    if (lim == LIM_NONE) return f(LimTag<LK_NONE>{});
+    if (lim == LIM_SUPERBEE) return f(LimTag<LK_SUPERBEE>{});
+    if constexpr (F32) {
+        if (lim == LIM_MINMOD) return f(LimTag<LK_MINMOD>{});
+    }
+    return f(LimTag<LK_THETA>{});
 }
 
 // Limited slope at an edge from three consecutive values along its axis.
@@ -141,6 +157,9 @@ __device__ __forceinline__ R limited_slope(R wm, R w0, R wp, R theta)
 {
     if constexpr (LK == LK_NONE) {
         return R(0);
+    } else if constexpr (LK == LK_MINMOD) {
+        static_assert(sizeof(R) == 4, "minmod has its own kind in float arithmetic only");
+        return __builtin_amdgcn_fmed3f(w0 - wm, wp - w0, 0.0f);
     } else if constexpr (sizeof(R) == 4 && LK == LK_SUPERBEE) {
         const float dm = w0 - wm, dp = wp - w0;
         const float s1 = __builtin_amdgcn_fmed3f(2.0f * dm, dp, 0.0f);
@@ -176,7 +195,10 @@ __device__ __forceinline__ float y_slope_carried(float wm, float w0, float wp, f
     } else {
         const float dp = wp - w0;
         float s, dps;
-        if constexpr (LK == LK_SUPERBEE) {
+        if constexpr (LK == LK_MINMOD) {
+            dps = dp;
+            s = __builtin_amdgcn_fmed3f(dm, dp, 0.0f);
+        } else if constexpr (LK == LK_SUPERBEE) {
             dps = 2.0f * dp;
             const float s1 = __builtin_amdgcn_fmed3f(dms, dp, 0.0f);
             const float s2 = __builtin_amdgcn_fmed3f(dm, dps, 0.0f);
@@ -925,39 +947,18 @@ __global__ __launch_bounds__(kBlock) void stage_kernel_batched(const InstDev *__
     const int local = (int)(tile - I.tile_begin);
     const int strip = local % I.strips, chunk = local / I.strips;
     const int lane = threadIdx.x & 63;
-    const int lk = limiter_kind(I.limiter);
-    if constexpr (FD) {
-        if (I.vkind == VK_PRESCRIBED_FD) {
-            if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane, half);
-            else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane, half);
-            else run_tile<R, S, LK_THETA, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane, half);
-            return;
+    with_limiter<sizeof(R) == 4>(I.limiter, [&](auto t) {
+        constexpr int L = decltype(t)::value;
+        if constexpr (FD) {
+            if (I.vkind == VK_PRESCRIBED_FD) run_tile<R, S, L, VK_PRESCRIBED_FD, false, MODE>(I, strip, chunk, lane, half);
+            else if (I.v0f != nullptr) run_tile<R, S, L, VK_LAW_FD, true, MODE>(I, strip, chunk, lane, half);
+            else run_tile<R, S, L, VK_LAW_FD, false, MODE>(I, strip, chunk, lane, half);
+        } else {
+            if (I.vkind == VK_PRESCRIBED) run_tile<R, S, L, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane, half);
+            else if (I.v0f != nullptr) run_tile<R, S, L, VK_LAW, true, MODE>(I, strip, chunk, lane, half);
+            else run_tile<R, S, L, VK_LAW, false, MODE>(I, strip, chunk, lane, half);
         }
-        if (I.vkind == VK_LAW_FD) {
-            if (I.v0f != nullptr) {
-                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane, half);
-                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, true, MODE>(I, strip, chunk, lane, half);
-                else run_tile<R, S, LK_THETA, VK_LAW_FD, true, MODE>(I, strip, chunk, lane, half);
-            } else {
-                if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane, half);
-                else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW_FD, false, MODE>(I, strip, chunk, lane, half);
-                else run_tile<R, S, LK_THETA, VK_LAW_FD, false, MODE>(I, strip, chunk, lane, half);
-            }
-        }
-        return;
-    } else if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane, half);
-        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane, half);
-        else run_tile<R, S, LK_THETA, VK_PRESCRIBED, false, MODE>(I, strip, chunk, lane, half);
-    } else if (I.v0f != nullptr) {
-        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW, true, MODE>(I, strip, chunk, lane, half);
-        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW, true, MODE>(I, strip, chunk, lane, half);
-        else run_tile<R, S, LK_THETA, VK_LAW, true, MODE>(I, strip, chunk, lane, half);
-    } else {
-        if (lk == LK_NONE) run_tile<R, S, LK_NONE, VK_LAW, false, MODE>(I, strip, chunk, lane, half);
-        else if (lk == LK_SUPERBEE) run_tile<R, S, LK_SUPERBEE, VK_LAW, false, MODE>(I, strip, chunk, lane, half);
-        else run_tile<R, S, LK_THETA, VK_LAW, false, MODE>(I, strip, chunk, lane, half);
-    }
+    });
 }
 
 template <typename R, typename S, int LK, int VK, bool FIELD, bool HSUM = false>
@@ -1022,22 +1023,12 @@ __global__ __launch_bounds__(kBlock) void fused_kernel_batched(const InstDev *__
     const int lane = threadIdx.x & 63;
     const void *s11 = DIR ? I.w11 : I.a11, *s12 = DIR ? I.w12 : I.a12;
     void *d11 = DIR ? I.a11 : I.w11, *d12 = DIR ? I.a12 : I.w12;
-    const int lk = limiter_kind(I.limiter);
-    if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_PRESCRIBED, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else if (lk == LK_SUPERBEE)
-            run_tile_fused<LK_SUPERBEE, VK_PRESCRIBED, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else run_tile_fused<LK_THETA, VK_PRESCRIBED, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-    } else if (I.v0f != nullptr) {
-        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, true, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else if (lk == LK_SUPERBEE) run_tile_fused<LK_SUPERBEE, VK_LAW, true, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else run_tile_fused<LK_THETA, VK_LAW, true, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-    } else {
-        if (lk == LK_NONE) run_tile_fused<LK_NONE, VK_LAW, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else if (lk == LK_SUPERBEE)
-            run_tile_fused<LK_SUPERBEE, VK_LAW, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-        else run_tile_fused<LK_THETA, VK_LAW, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
-    }
+    with_limiter<true>(I.limiter, [&](auto t) {
+        constexpr int L = decltype(t)::value;
+        if (I.vkind == VK_PRESCRIBED) run_tile_fused<L, VK_PRESCRIBED, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else if (I.v0f != nullptr) run_tile_fused<L, VK_LAW, true, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
+        else run_tile_fused<L, VK_LAW, false, MID>(I, strip, chunk, lane, s11, s12, d11, d12);
+    });
 }
 
 template <int LK, int VK, bool FIELD, bool MID>
@@ -1052,54 +1043,27 @@ hipError_t launch_fused_t(const InstDev &I, int dir, hipStream_t s)
     return hipGetLastError();
 }
 
-// The fully discrete scheme: the same dispatch over the VK_FD kinds.
-template <typename R, typename S>
-hipError_t launch_stage_fd(const InstDev &I, int mode, hipStream_t s)
-{
-    const int lk = limiter_kind(I.limiter);
-    if (I.vkind == VK_PRESCRIBED_FD) {
-        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_PRESCRIBED_FD, false>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_PRESCRIBED_FD, false>(I, mode, s);
-        return launch_stage_t<R, S, LK_THETA, VK_PRESCRIBED_FD, false>(I, mode, s);
-    }
-    if (I.v0f != nullptr && I.hsum != nullptr) {
-        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW_FD, true, true>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW_FD, true, true>(I, mode, s);
-        return launch_stage_t<R, S, LK_THETA, VK_LAW_FD, true, true>(I, mode, s);
-    }
-    if (I.v0f != nullptr) {
-        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW_FD, true>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW_FD, true>(I, mode, s);
-        return launch_stage_t<R, S, LK_THETA, VK_LAW_FD, true>(I, mode, s);
-    }
-    if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW_FD, false>(I, mode, s);
-    if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW_FD, false>(I, mode, s);
-    return launch_stage_t<R, S, LK_THETA, VK_LAW_FD, false>(I, mode, s);
-}
-
+// Dispatch of one instance's stage launch over limiter, Hamiltonian and
+// scheme, field presence, and the coupled runs' per-tile sums of Hhat.
 template <typename R, typename S>
 hipError_t launch_stage_r(const InstDev &I, int mode, hipStream_t s)
 {
-    const int lk = limiter_kind(I.limiter);
-    if ((I.vkind & VK_FD) != 0) return launch_stage_fd<R, S>(I, mode, s);
-    if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_PRESCRIBED, false>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_PRESCRIBED, false>(I, mode, s);
-        return launch_stage_t<R, S, LK_THETA, VK_PRESCRIBED, false>(I, mode, s);
-    }
-    if (I.v0f != nullptr && I.hsum != nullptr) {   // coupled runs: also the per-tile sums of Hhat
-        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW, true, true>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW, true, true>(I, mode, s);
-        return launch_stage_t<R, S, LK_THETA, VK_LAW, true, true>(I, mode, s);
-    }
-    if (I.v0f != nullptr) {
-        if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW, true>(I, mode, s);
-        if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW, true>(I, mode, s);
-        return launch_stage_t<R, S, LK_THETA, VK_LAW, true>(I, mode, s);
-    }
-    if (lk == LK_NONE) return launch_stage_t<R, S, LK_NONE, VK_LAW, false>(I, mode, s);
-    if (lk == LK_SUPERBEE) return launch_stage_t<R, S, LK_SUPERBEE, VK_LAW, false>(I, mode, s);
-    return launch_stage_t<R, S, LK_THETA, VK_LAW, false>(I, mode, s);
+    return with_limiter<sizeof(R) == 4>(I.limiter, [&](auto t) -> hipError_t {
+        constexpr int L = decltype(t)::value;
+        const bool field = I.v0f != nullptr, hsum = I.hsum != nullptr;
+        switch (I.vkind) {
+        case VK_PRESCRIBED: return launch_stage_t<R, S, L, VK_PRESCRIBED, false>(I, mode, s);
+        case VK_PRESCRIBED_FD: return launch_stage_t<R, S, L, VK_PRESCRIBED_FD, false>(I, mode, s);
+        case VK_LAW_FD:
+            if (field && hsum) return launch_stage_t<R, S, L, VK_LAW_FD, true, true>(I, mode, s);
+            if (field) return launch_stage_t<R, S, L, VK_LAW_FD, true>(I, mode, s);
+            return launch_stage_t<R, S, L, VK_LAW_FD, false>(I, mode, s);
+        default:
+            if (field && hsum) return launch_stage_t<R, S, L, VK_LAW, true, true>(I, mode, s);
+            if (field) return launch_stage_t<R, S, L, VK_LAW, true>(I, mode, s);
+            return launch_stage_t<R, S, L, VK_LAW, false>(I, mode, s);
+        }
+    });
 }
 
 template <typename R, typename S>

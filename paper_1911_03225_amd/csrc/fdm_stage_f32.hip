@@ -19,21 +19,13 @@ namespace {
 template <bool MID>
 hipError_t launch_fused_r(const InstDev &I, int dir, hipStream_t s)
 {
-    const int lk = limiter_kind(I.limiter);
-    if (I.vkind == VK_PRESCRIBED) {
-        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_PRESCRIBED, false, MID>(I, dir, s);
-        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_PRESCRIBED, false, MID>(I, dir, s);
-        return launch_fused_t<LK_THETA, VK_PRESCRIBED, false, MID>(I, dir, s);
-    }
-    if (I.vkind != VK_LAW) return hipErrorInvalidValue;   // semi-discrete scheme only
-    if (I.v0f != nullptr) {
-        if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, true, MID>(I, dir, s);
-        if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, true, MID>(I, dir, s);
-        return launch_fused_t<LK_THETA, VK_LAW, true, MID>(I, dir, s);
-    }
-    if (lk == LK_NONE) return launch_fused_t<LK_NONE, VK_LAW, false, MID>(I, dir, s);
-    if (lk == LK_SUPERBEE) return launch_fused_t<LK_SUPERBEE, VK_LAW, false, MID>(I, dir, s);
-    return launch_fused_t<LK_THETA, VK_LAW, false, MID>(I, dir, s);
+    if (I.vkind != VK_LAW && I.vkind != VK_PRESCRIBED) return hipErrorInvalidValue;   // semi-discrete scheme only
+    return with_limiter<true>(I.limiter, [&](auto t) -> hipError_t {
+        constexpr int L = decltype(t)::value;
+        if (I.vkind == VK_PRESCRIBED) return launch_fused_t<L, VK_PRESCRIBED, false, MID>(I, dir, s);
+        if (I.v0f != nullptr) return launch_fused_t<L, VK_LAW, true, MID>(I, dir, s);
+        return launch_fused_t<L, VK_LAW, false, MID>(I, dir, s);
+    });
 }
 }  // namespace
 

@@ -290,3 +290,20 @@ def batched_instances(seed: int = 5, counts=BATCH_COUNTS, sizes=BATCH_SIZES):
             s = int(rng.integers(0, 2**31 - 1))
             out.append(Instance(nx, ny, lim, vel, v0, init, s))
     return out
+
+
+def stratified_subset(instances, large_nodes=None):
+    """One instance per (size, velocity, limiter) class, in workload order.
+    Sizes of more than large_nodes nodes (when given) keep only their first
+    instance, so that an oracle pass over the subset stays short."""
+    seen, sizes, out = set(), set(), []
+    for inst in instances:
+        key = (inst.nx, inst.ny, inst.velocity, inst.limiter)
+        if key in seen:
+            continue
+        if large_nodes is not None and inst.nx * inst.ny > large_nodes and (inst.nx, inst.ny) in sizes:
+            continue
+        seen.add(key)
+        sizes.add((inst.nx, inst.ny))
+        out.append(inst)
+    return out

@@ -284,3 +284,4 @@ def test_missing_library_fails_loudly(fdm, monkeypatch, tmp_path):
     monkeypatch.setattr(fdm, "_lib", None)
     with pytest.raises(RuntimeError, match="not found"):
         fdm.load_library(str(tmp_path / "libfdm.so"))
+

@@ -1,10 +1,13 @@
-"""Host logic of bench.py (no GPU): the traffic summary lookup, the tile
-height recovered from a launch's grid size, and the one-GPU guard."""
+"""Host logic of bench.py (no GPU): the counter summary written from
+rocprofv3 CSVs and its lookup, the parity records, the coupled-curve
+comparison, the host description and the one-GPU guard."""
+import csv
 import json
 import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -12,60 +15,82 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def _launch_threads(n, rows, strip):
-    """Threads of one launch: 4-wave blocks, rounded up to 8 blocks (one per XCD)."""
-    tiles = -(-n // strip) * -(-n // rows)
-    blocks = -(-tiles // 4)
-    return -(-blocks // 8) * 8 * 256
+def _csv(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "x_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"], r)))
 
 
-@pytest.mark.parametrize("rows", [1, 4, 12, 15, 19, 25, 64])
-def test_rows_from_grid_inverts_the_launch_shape(rows):
-    for strip in (56, 60):
-        got = bench.rows_from_grid(_launch_threads(2048, rows, strip), 2048, strip)
-        # the smallest height with the same launch shape
-        assert got is not None and got <= rows
-        assert _launch_threads(2048, got, strip) == _launch_threads(2048, rows, strip)
+def test_profile_summary_calibrates_by_the_copy_kernel(tmp_path, monkeypatch):
+    """FETCH_SIZE and WRITE_SIZE are scaled by what they read for a copy of
+    known size; SQ counters are averaged per launch."""
+    k = "void fdm::(anonymous namespace)::" + bench.HEADLINE_KERNEL + "(fdm::InstDev, long, int, int, int)"
+    c = "void fdm::(anonymous namespace)::" + bench.COPY_KERNEL + "(float*, float const*, long)"
+    n = 1024                                   # copy of 4 MiB each way = 4096 KiB
+    _csv(str(tmp_path / "f"), [(k, 1, "FETCH_SIZE", 1000), (k, 1, "FETCH_SIZE", 1200), (c, 1, "FETCH_SIZE", 2048)])
+    _csv(str(tmp_path / "w"), [(k, 1, "WRITE_SIZE", 3000), (c, 1, "WRITE_SIZE", 4096)])
+    _csv(str(tmp_path / "s"), [(k, 1, "SQ_INSTS_VALU", 100.0), (k, 1, "SQ_INSTS_VALU", 300.0),
+                               (k, 1, "SQ_INSTS_MFMA", 0.0), (k, 1, "SQ_WAVES", 50.0)])
+    out = tmp_path / "p.json"
+    bench.write_profile_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s"), str(out), n, 43)
+    p = json.loads(out.read_text())
+    assert p["fetch_factor"] == 2.0 and p["write_factor"] == 1.0
+    assert p["bytes_per_launch"] == round((1100 * 2.0 + 3000 * 1.0) * 1024)
+    assert p["sq_per_launch"] == {"SQ_INSTS_VALU": 200.0, "SQ_INSTS_MFMA": 0.0, "SQ_WAVES": 50.0}
+    assert p["tile_rows"] == 43 and p["kernel_source_sha256"] == bench.kernel_source_hash()
+    # looked up only at the profiled height, and only while the kernels are unchanged
+    monkeypatch.setattr(bench, "PROFILE_FILE", str(out))
+    assert bench.load_profile(43)["bytes_per_launch"] == p["bytes_per_launch"]
+    assert bench.load_profile(42) is None
+    p["kernel_source_sha256"] = "0" * 64
+    out.write_text(json.dumps(p))
+    assert bench.load_profile(43) is None
 
 
-def _summary(tmp_path, monkeypatch, **extra):
-    s = {"kernel_source_sha256": bench.kernel_source_hash(), "grid": 2048, "tile_rows": 12,
-         "stage": {"fused": {"bytes": 700, "tile_rows": 12}}, "bytes_per_launch": 900,
-         "fused_by_rows": {"15": {"bytes": 750}, "19": {"bytes": 760}}}
-    s.update(extra)
-    path = tmp_path / "traffic.json"
-    path.write_text(json.dumps(s))
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+def test_parity_record_hand_values():
+    a = (np.array([[1.0, -1.0]], np.float32), np.array([[2.0, 0.0]], np.float32))    # sum|a| 4, max 2
+    o = (np.array([[1.0, -1.0]]), np.array([[1.5, 0.5]]))
+    g = (np.array([[1.0, -0.5]]), np.array([[1.5, 0.5]]))
+    r = bench.parity_record(g, o, a, 7, 1e-5)
+    assert r["rel_l1"] == pytest.approx(0.5 / 4) and r["rel_linf"] == pytest.approx(0.5 / 2)
+    # totals: a11 0 -> 0.5 (g), a12 2 -> 2
+    assert r["drift"] == pytest.approx(0.5 / 4) and r["oracle_drift"] == 0.0
+    assert r["steps"] == 7 and r["bar_rel_l1"] == 1e-5
 
 
-def test_traffic_lookup_by_height(tmp_path, monkeypatch):
-    _summary(tmp_path, monkeypatch)
-    assert bench.load_traffic(2048, "fp32", "superbee", 15, fused=True) == (750, 15)
-    assert bench.load_traffic(2048, "fp32", "superbee", 19, fused=True) == (760, 19)
-    # a fused height the passes did not cover: the profiled entry, with its height
-    assert bench.load_traffic(2048, "fp32", "superbee", 13, fused=True) == (700, 12)
-    # unfused: only at the profiled height
-    assert bench.load_traffic(2048, "fp32", "superbee", 12) == (900, 12)
-    assert bench.load_traffic(2048, "fp32", "superbee", 16) is None
-    # other workloads have no summary
-    assert bench.load_traffic(4096, "fp32", "superbee", 12) is None
-    assert bench.load_traffic(2048, "fp64", "superbee", 12) is None
-    assert bench.load_traffic(2048, "fp32", "mc", 12) is None
+def test_coupled_curve_parity(tmp_path, monkeypatch):
+    ref = [{"step": 100 * (i + 1), "eps13": 0.01 * (i + 1), "sigma13": 0.02 * (i + 1), "phi_mean": -0.01,
+            "sum_abs": 10.0} for i in range(3)]
+    cols = ["step", "eps13", "sigma13", "phi_mean", "sum_abs"]
+    path = tmp_path / "g.json"
+    path.write_text(json.dumps({"columns": cols, "history": [[r[c] for c in cols] for r in ref]}))
+    monkeypatch.setattr(bench, "GOLDEN_C4", str(path))
+    hist = [dict(r) for r in ref]
+    hist[1]["sigma13"] += 0.0006                   # over max |sigma13| = 0.06: 1e-2
+    hist[2]["sum_abs"] -= 0.2                      # over s0 = 20: 1e-2
+    out = bench.coupled_curve_parity({"hist": hist, "s0": 20.0, "steps": 5000})
+    assert out["sigma13_max_dev"] == pytest.approx(1e-2) and out["sum_abs_max_dev"] == pytest.approx(1e-2)
+    assert out["eps13_max_dev"] == 0.0 and out["records"] == 3
+    assert bench.coupled_curve_parity({"hist": hist, "s0": 20.0, "steps": 100}) is None
 
 
-def test_traffic_ignored_once_the_kernels_change(tmp_path, monkeypatch):
-    _summary(tmp_path, monkeypatch, kernel_source_sha256="0" * 64)
-    assert bench.load_traffic(2048, "fp32", "superbee", 12) is None
-    assert bench.load_traffic(2048, "fp32", "superbee", 15, fused=True) is None
+def test_host_description():
+    h = bench.host_description()
+    assert h["nproc"] == os.cpu_count() and "cpu_model" in h and "OMP_NUM_THREADS" in h
 
 
-def test_committed_traffic_summary_is_well_formed():
+def test_committed_counter_summary_is_well_formed():
     # (bench.py reports it only while its source hash matches the kernels)
-    with open(bench.TRAFFIC_FILE) as fh:
+    if not os.path.exists(bench.PROFILE_FILE):
+        pytest.skip("no counter summary committed yet")
+    with open(bench.PROFILE_FILE) as fh:
         t = json.load(fh)
-    assert len(t["kernel_source_sha256"]) == 64
-    assert t["grid"] == 2048 and t["bytes_per_launch"] > 0 and t["fused_by_rows"]
+    assert len(t["kernel_source_sha256"]) == 64 and t["grid"] == 4096 and t["bytes_per_launch"] > 0
     assert 1.9 < t["fetch_factor"] < 2.1 and 0.9 < t["write_factor"] < 1.1
+    assert t["sq_per_launch"]["SQ_INSTS_VALU"] > 0 and t["sq_per_launch"].get("SQ_INSTS_MFMA", 0) == 0
 
 
 def test_more_than_one_gpu_is_refused():
