@@ -384,6 +384,31 @@ typedef struct fdm_tune_trial {
 fdm_status fdm_autotune(fdm_ctx *ctx, void *const *alpha11, void *const *alpha12, int32_t trial_steps,
                         fdm_tune_trial *trials, int32_t max_trials, int32_t *n_trials);
 
+/* Allocation-free step, for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc).  It advances one
+ * instance by n_steps >= 0 steps exactly as fdm_transport_init(desc, 1, NULL
+ * options, hip_stream) + fdm_transport_step + fdm_destroy would -- the same
+ * checks, step, kernels, default tile height and result bits -- with float32
+ * density arrays (alpha11, alpha12: device arrays of nx*ny floats, read and
+ * written in place, distinct), but allocates nothing: the stage buffer and
+ * the max |v0| partials live in a static device array of
+ * 8 * FDM_NOALLOC_MAX_NODES + 1 KiB bytes (32 MiB), which each GPU the
+ * library runs on holds until the process ends.
+ *   Limit: nx*ny <= FDM_NOALLOC_MAX_NODES (a 2048 x 2048 grid), else
+ *   FDM_ERR_INVALID_ARG.
+ *   Sharing: every call on a GPU uses that GPU's one array.  Calls on one
+ *   stream are ordered; calls that overlap on one GPU (several streams or
+ *   threads) race on the array and give wrong results.  Nothing in it needs
+ *   to start at zero (each call writes before it reads).
+ *   Synchronisation: asynchronous, except with a celerity field (v0_field),
+ *   whose max |v0| is read back (the stream is synchronized once).
+ *   Errors: FDM_ERR_INVALID_ARG, FDM_ERR_CFL (checked on the host before any
+ *   HIP call, except the bound of a fixed dt over a field), FDM_ERR_DEVICE;
+ *   the message is in fdm_last_error(NULL).  No context, nothing sticky. */
+#define FDM_NOALLOC_MAX_NODES 4194304
+fdm_status fdm_transport_step_noalloc(const fdm_transport_desc *desc, void *alpha11, void *alpha12,
+                                      int32_t n_steps, void *hip_stream);
+
 /* Release the context and its workspace (waits for its pending work).
  * NULL is a no-op. */
 void fdm_destroy(fdm_ctx *ctx);

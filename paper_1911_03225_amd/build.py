@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libfdm.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
            ("fdm_kernels.hip", "fdm_stage_f32.hip", "fdm_stage_f64.hip", "fdm_static.hip", "fdm_host.hip",
-            "fdm_api.hip")]
+            "fdm_api.hip", "fdm_noalloc.hip")]
 # rocFFT for the static solve's transforms
 LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = "gfx950"

@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdm_transport_init.argtypes = [P(fdm_transport_desc), i32, P(fdm_options), vp, P(vp)]
     lib.fdm_transport_step.argtypes = [vp, fpp, fpp, i32]
     lib.fdm_transport_stats.argtypes = [vp, fpp, fpp, P(fdm_stats)]
+    lib.fdm_transport_step_noalloc.argtypes = [P(fdm_transport_desc), vp, vp, i32, vp]
     lib.fdm_static_solve.argtypes = [P(fdm_static_desc), vp, vp, vp, vp]
     lib.fdm_run.argtypes = [vp, P(fdm_loading), fpp, fpp, i32, i32, P(fdm_stats)]
     lib.fdm_transport_dt.argtypes = [vp, i32]
@@ -136,7 +137,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdm_last_error.argtypes = [vp]
     lib.fdm_last_error.restype = ctypes.c_char_p
     for name in ("fdm_transport_init", "fdm_transport_step", "fdm_transport_stats",
-                 "fdm_static_solve", "fdm_run", "fdm_autotune"):
+                 "fdm_static_solve", "fdm_run", "fdm_autotune", "fdm_transport_step_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -260,6 +261,18 @@ def fdm_transport_step(ctx, alpha11, alpha12, n_steps: int) -> None:
     p11, p12 = _ptr_arrays(ctx, alpha11, alpha12)
     _check(load_library().fdm_transport_step(ctx.handle, p11, p12, int(n_steps)),
            "fdm_transport_step", ctx)
+
+
+NOALLOC_MAX_NODES = 4194304
+
+
+def fdm_transport_step_noalloc(desc_, alpha11, alpha12, n_steps: int, stream=None) -> None:
+    """Allocation-free step of one float32 instance (no context)."""
+    shape = (desc_.ny, desc_.nx)
+    st = load_library().fdm_transport_step_noalloc(ctypes.byref(desc_), _ptr(alpha11, shape, "alpha11"),
+                                                   _ptr(alpha12, shape, "alpha12"), int(n_steps),
+                                                   _stream_handle(stream))
+    _check(st, "fdm_transport_step_noalloc", None)
 
 
 def fdm_transport_stats(ctx, alpha11, alpha12, allow_nonfinite: bool = False):

@@ -285,3 +285,28 @@ def test_missing_library_fails_loudly(fdm, monkeypatch, tmp_path):
     with pytest.raises(RuntimeError, match="not found"):
         fdm.load_library(str(tmp_path / "libfdm.so"))
 
+
+def test_noalloc_step_rejects_on_host(fdm):
+    """The allocation-free step validates before any HIP call: a grid above
+    its maximum, a bad descriptor, NULL or aliased arrays, a step above the
+    stability bound."""
+    import ctypes
+    lib = fdm.load_library()
+    p, q = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    n = fdm.NOALLOC_MAX_NODES
+    cases = [
+        (fdm.desc(n + 1, 1), p, q, fdm.FDM_ERR_INVALID_ARG, "maximum"),
+        (fdm.desc(2049, 2048), p, q, fdm.FDM_ERR_INVALID_ARG, "maximum"),
+        (fdm.desc(0, 16), p, q, fdm.FDM_ERR_INVALID_ARG, "nx and ny"),
+        (fdm.desc(16, 16), None, q, fdm.FDM_ERR_INVALID_ARG, "NULL"),
+        (fdm.desc(16, 16), p, p, fdm.FDM_ERR_INVALID_ARG, "alias"),
+        (fdm.desc(16, 16, cfl=0.6), p, q, fdm.FDM_ERR_CFL, "2-D Courant"),
+        (fdm.desc(16, 16, cfl=0.3, time_order=1), p, q, fdm.FDM_ERR_CFL, "forward-Euler"),
+    ]
+    for d, a, b, st, msg in cases:
+        assert lib.fdm_transport_step_noalloc(ctypes.byref(d), a, b, 1, None) == st, msg
+        assert msg in fdm.fdm_last_error(None)
+    assert lib.fdm_transport_step_noalloc(None, p, q, 1, None) == fdm.FDM_ERR_INVALID_ARG
+    assert lib.fdm_transport_step_noalloc(ctypes.byref(fdm.desc(16, 16)), p, q, -1, None) == fdm.FDM_ERR_INVALID_ARG
+    # zero steps: validated, then nothing to do (no HIP call)
+    assert lib.fdm_transport_step_noalloc(ctypes.byref(fdm.desc(n, 1)), p, q, 0, None) == fdm.FDM_OK
