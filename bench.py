@@ -166,7 +166,7 @@ def single_instance(fdm, a11, a12, K, W, repeats, stream, desc_kw, options, auto
     sched = "plain" if sched == "auto" else sched
     trials, choice = None, "fixed" if options.get("tile_rows") else "default rule"
     if autotune:
-        trials = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=5)
+        trials = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=20)
         best = min(trials, key=lambda t: t["seconds_per_step"])
         sched, choice = best["schedule"], "autotuned"
         near = [t for t in trials if t["schedule"] == "fused" and t["tile_rows"] == prefer_rows and
@@ -286,8 +286,9 @@ def fully_discrete_leg(fdm, W_, K, warm, repeats, autotune, log):
 def c1_leg(fdm, W_, log):
     """The small plain case at full length: 64^2 colliding pulses, LAW
     v0 = -1, minmod, Heun, Courant 0.5, 400 steps."""
+    import numpy as np
     import torch
-    a11, a12 = W_.colliding_pulses(64)
+    a11, a12 = (np.ascontiguousarray(a) for a in W_.colliding_pulses(64))
     stream = torch.cuda.current_stream()
     t11, t12 = torch.from_numpy(a11).to("cuda:0"), torch.from_numpy(a12).to("cuda:0")
     ctx = fdm.fdm_transport_init(fdm.desc(64, 64, limiter="minmod", cfl=0.5, v0=-1.0), stream=stream)

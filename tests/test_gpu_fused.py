@@ -86,7 +86,8 @@ def test_fused_midpoint_batched_and_oracle(fdm, oracle):
         assert np.array_equal(f11, p11) and np.array_equal(f12, p12)
 
 
-@pytest.mark.parametrize("nx,ny", [(1, 1), (3, 5), (55, 9), (56, 2), (57, 3), (113, 67), (200, 1), (1, 40)])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 3), (3, 5), (55, 9), (56, 2), (57, 3), (113, 67), (119, 9), (120, 2),
+                                   (121, 3), (200, 1), (239, 7), (241, 5), (1, 40)])
 def test_fused_odd_sizes_bitwise(fdm, nx, ny):
     rng = np.random.default_rng(nx * 1000 + ny)
     phi = rng.normal(size=(ny, nx))
