@@ -744,17 +744,21 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
 // ------------------------------------------------------------ fused Heun
 //
 // Both Heun stages in one pass (float only, semi-discrete scheme): each wave
-// runs the first stage two node rows ahead of the second and keeps the
+// runs the first stage three node rows ahead of the second and keeps the
 // first stage's densities in registers, so a step reads the state (and the
 // celerity field) once and writes the new state once -- 8 B per node in and
 // out instead of 20 and 28 for the two unfused launches.  The second stage
 // needs first-stage values two lanes and two rows beyond its outputs, so a
 // wave owns 56 output columns (4 halo lanes on each side) and the first
-// stage runs four rows beyond the tile.  Every value is computed with the
+// stage runs two rows above the tile and two (plus one unused) below.  Every value is computed with the
 // same operations as in the unfused kernels (same node function, same
 // updates), so the result is the same bit for bit.  Reads src, writes dst
 // (distinct buffers: neighbouring tiles still read src).
 constexpr int kFStrip = kFusedStrip, kFHalo = 4;
+// The fused kernel's loads run kFAhead rows ahead of stage A (at most five:
+// A's alpha_11 ring holds rows m-1 .. m+kFAhead+1 in eight slots).
+constexpr int kFAhead = 2;
+static_assert(kFAhead >= 1 && kFAhead <= 5, "fused look-ahead must fit the eight-slot rings");
 
 template <int LK, int VK, bool FIELD, bool MID = false>
 __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int chunk, int lane, const void *src11,
@@ -777,37 +781,44 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
     const int nrows = min(I.rows, ny - k0);
     const uint32_t off_st = out_col ? off : kSkip;
 
-    // Iteration i (0 .. nrows + 4): the first stage ("A") at node row
-    // m = k0 - 2 + i, then, from i = 4 on, the second stage ("B") at node
-    // row k = m - 2.  Ring slots, with p = i & 7: input alpha_11 of row
-    // mA0 + j in y[j & 7] (A reads rows m-1 .. m+1, B the base row m-3, loads
-    // run to m+3), input alpha_12 and v0 of row mA0 + j in slot j & 7 (A row
-    // m, B base row m-2, loads to m+2); A's outputs alpha_12 of row m in
-    // wxo[p & 3] and alpha_11 of row m-1 in wyo[(p + 3) & 3].
-    S y[8], wx_[8], wxo[4], wyo[4];
-    float v0_[8];
+    // Iteration i: the first stage ("A") at node row m = k0 - 2 + i, for
+    // i = 0 .. nrows + 5, and, from i = 5 on, the second stage ("B") at node
+    // row k = m - 3 (k0 .. k0 + nrows).  B lags A by three rows, one more
+    // than its stencil needs, so that it reads only what A produced on
+    // earlier iterations: the two node evaluations of an iteration are
+    // independent and the compiler can interleave their instructions.  The
+    // last iteration evaluates A on one row more than B needs, from loads
+    // the range check has zeroed; nothing reads those results.  Ring slots
+    // (mA0 = k0 - 2): input alpha_11 of row mA0 + j in y[j & 7] (A reads rows
+    // m-1 .. m+1, loads run to m+kFAhead+1), input alpha_12 and v0 of row
+    // mA0 + j in slot j & 7 (A row m, loads to m+kFAhead); for B, A's outputs
+    // alpha_12 and alpha_11 of row mA0 + j in wxo[j & 3] and wyo[j & 3]
+    // (written on iterations j and j + 1) and the step's initial alpha_11,
+    // alpha_12 and v0 of that row in b11_[j & 3], b12_[j & 3], vb_[j & 3]
+    // (copied from A's operands).
+    S y[8], wx_[8], wxo[4], wyo[4], b11_[4], b12_[4];
+    float v0_[8], vb_[4];
     R slA[2], hhA[2], slB[2], hhB[2];
     for (int j = 0; j < 8; ++j) v0_[j] = 0.0f;
-    for (int j = 0; j < 4; ++j) wxo[j] = wyo[j] = S(0);
-    slB[0] = slB[1] = hhB[0] = hhB[1] = R(0);
-    float ydmB = 0.0f, ydmsB = 0.0f;
+    for (int j = 0; j < 4; ++j) vb_[j] = 0.0f;
 
     int k = (k0 - 4) % ny;   // A starts at node row mA0 = k0 - 2
     if (k < 0) k += ny;
     const R ym2 = R(at(row_ptr<S>(src11, k, nx), off));
     k = next_row(k, ny);
     y[7] = at(row_ptr<S>(src11, k, nx), off);
-    int kA = next_row(k, ny);                  // A's node row
-    y[0] = at(row_ptr<S>(src11, kA, nx), off);
+    int kf = next_row(k, ny);   // row of the next alpha_12 / v0 fetch
+    y[0] = at(row_ptr<S>(src11, kf, nx), off);
     slA[1] = limited_slope<LK>(ym2, R(y[7]), R(y[0]), theta);
     hhA[1] = R(0);
     float ydmA = float(R(y[0]) - R(y[7]));
     float ydmsA = LK == LK_SUPERBEE ? 2.0f * ydmA : float(theta) * ydmA;
+    float ydmB = 0.0f, ydmsB = 0.0f;   // set after the first five iterations
 
-    const int last = nrows + 4;   // the last iteration
-    int kf = kA;
+    const int lastA = nrows + 4;   // A's last row that B needs
+    const int last = nrows + 5;    // B's last iteration
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j) {
+    for (int j = 0; j < kFAhead; ++j) {
         const int kf1 = next_row(kf, ny);
         wx_[j] = at(row_ptr<S>(src12, kf, nx), off);
         y[j + 1] = at(row_ptr<S>(src11, kf1, nx), off);
@@ -832,80 +843,94 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
         return numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
     };
 
-    auto body = [&](int it, auto phase) {
+    // Stage A on iteration it (ring phase p = it & 7).
+    auto stage_a = [&](int it, auto phase) {
         constexpr int p = decltype(phase)::value;
         constexpr int h = p & 1, hp = h ^ 1;
-        // ---- stage A at node row kA
-        {
-            const R ym1 = R(y[(p + 7) & 7]), y0 = R(y[p]), yp1 = R(y[(p + 1) & 7]);
-            const R wx = R(wx_[p]);
-            const R v0 = FIELD ? R(v0_[p]) : R(I.v0);
-            {   // operands of A's row m + kAhead (none past the last iteration)
-                const bool live = it + kAhead <= last;
-                wx_[(p + kAhead) & 7] = at(row_ptr<S>(src12, kf, nx, live), off);
-                y[(p + kAhead + 1) & 7] = at(row_ptr<S>(src11, kf1, nx, live), off);
-                if constexpr (FIELD) v0_[(p + kAhead) & 7] = at(row_ptr<float>(I.v0f, kf, nx, live), off);
-                kf = kf1;
-                kf1 = next_row(kf1, ny);
-            }
-            const R hv = node(ym1, y0, yp1, wx, v0, slA, h, hp, ydmA, ydmsA);
-            const R hr = from_right(hv);
-            const R hprev = hhA[hp];
-            hhA[h] = hv;
-            wxo[p & 3] = S(madd(-cxa, hr - hv, wx));          // alpha_12 of row m after stage 1
-            wyo[(p + 3) & 3] = S(madd(cya, hv - hprev, ym1));  // alpha_11 of row m-1 after stage 1
-            kA = next_row(kA, ny);
+        const R ym1 = R(y[(p + 7) & 7]), y0 = R(y[p]), yp1 = R(y[(p + 1) & 7]);
+        const R wx = R(wx_[p]);
+        const R v0 = FIELD ? R(v0_[p]) : R(I.v0);
+        b11_[(p + 3) & 3] = y[(p + 7) & 7];   // row m-1
+        b12_[p & 3] = wx_[p];                 // row m
+        if constexpr (FIELD) vb_[p & 3] = v0_[p];
+        {   // operands of A's row m + kFAhead (none past A's last useful row)
+            const bool live = it + kFAhead <= lastA;
+            wx_[(p + kFAhead) & 7] = at(row_ptr<S>(src12, kf, nx, live), off);
+            y[(p + kFAhead + 1) & 7] = at(row_ptr<S>(src11, kf1, nx, live), off);
+            if constexpr (FIELD) v0_[(p + kFAhead) & 7] = at(row_ptr<float>(I.v0f, kf, nx, live), off);
+            kf = kf1;
+            kf1 = next_row(kf1, ny);
         }
-        if (it < 4) return;
-        // ---- stage B at node row kB = m - 2
-        if (it == 4) {   // slope at edge k0-1/2 from stage-1 rows k0-2 .. k0
-            const R a = R(wyo[p & 3]), b = R(wyo[(p + 1) & 3]), c = R(wyo[(p + 2) & 3]);
-            slB[hp] = limited_slope<LK>(a, b, c, theta);
-            ydmB = float(c - b);
-            ydmsB = LK == LK_SUPERBEE ? 2.0f * ydmB : float(theta) * ydmB;
-            hhB[hp] = R(0);
-        }
-        {
-            const int bi = it - 4;
-            const R ym1 = R(wyo[(p + 1) & 3]), y0 = R(wyo[(p + 2) & 3]), yp1 = R(wyo[(p + 3) & 3]);
-            const R wx = R(wxo[(p + 2) & 3]);
-            const R v0 = FIELD ? R(v0_[(p + 6) & 7]) : R(I.v0);
-            const R b12 = R(wx_[(p + 6) & 7]), b11 = R(y[(p + 5) & 7]);   // the step's initial state
-            const R hv = node(ym1, y0, yp1, wx, v0, slB, h, hp, ydmB, ydmsB);
-            const R hr = from_right(hv);
-            const R hprev = hhB[hp];
-            hhB[h] = hv;
-            {   // Heun: the mean of the state and one more stage; midpoint: the state plus a full step
-                R nv = madd(-cx, hr - hv, MID ? b12 : wx);
-                if constexpr (!MID) nv = madd(R(0.5), b12, R(0.5) * nv);
-                put(row_ptr<S>(dst12, kB, nx, bi < nrows), off_st, S(nv));
-            }
-            {
-                R nv = madd(cy, hv - hprev, MID ? b11 : ym1);
-                if constexpr (!MID) nv = madd(R(0.5), b11, R(0.5) * nv);
-                put(row_ptr<S>(dst11, kBprev, nx, bi > 0), off_st, S(nv));
-            }
-            kBprev = kB;
-            kB = next_row(kB, ny);
-        }
+        const R hv = node(ym1, y0, yp1, wx, v0, slA, h, hp, ydmA, ydmsA);
+        const R hr = from_right(hv);
+        const R hprev = hhA[hp];
+        hhA[h] = hv;
+        wxo[p & 3] = S(madd(-cxa, hr - hv, wx));          // alpha_12 of row m after stage 1
+        wyo[(p + 3) & 3] = S(madd(cya, hv - hprev, ym1));  // alpha_11 of row m-1 after stage 1
     };
 
-    for (int it = 0;; it += 8) {
-        body(it, Phase<0>{});
+    // Stage B on iteration it (it >= 5), at node row kB = m - 3.
+    auto stage_b = [&](int it, auto phase) {
+        constexpr int p = decltype(phase)::value;
+        constexpr int h = p & 1, hp = h ^ 1;
+        const int bi = it - 5;
+        const R ym1 = R(wyo[p & 3]), y0 = R(wyo[(p + 1) & 3]), yp1 = R(wyo[(p + 2) & 3]);
+        const R wx = R(wxo[(p + 1) & 3]);
+        const R v0 = FIELD ? R(vb_[(p + 1) & 3]) : R(I.v0);
+        const R b12 = R(b12_[(p + 1) & 3]), b11 = R(b11_[p & 3]);   // the step's initial state
+        const R hv = node(ym1, y0, yp1, wx, v0, slB, h, hp, ydmB, ydmsB);
+        const R hr = from_right(hv);
+        const R hprev = hhB[hp];
+        hhB[h] = hv;
+        {   // Heun: the mean of the state and one more stage; midpoint: the state plus a full step
+            R nv = madd(-cx, hr - hv, MID ? b12 : wx);
+            if constexpr (!MID) nv = madd(R(0.5), b12, R(0.5) * nv);
+            put(row_ptr<S>(dst12, kB, nx, bi < nrows), off_st, S(nv));
+        }
+        {
+            R nv = madd(cy, hv - hprev, MID ? b11 : ym1);
+            if constexpr (!MID) nv = madd(R(0.5), b11, R(0.5) * nv);
+            put(row_ptr<S>(dst11, kBprev, nx, bi > 0), off_st, S(nv));
+        }
+        kBprev = kB;
+        kB = next_row(kB, ny);
+    };
+
+    // A alone on rows k0-2 .. k0+2 (iterations 0 .. 4).
+    stage_a(0, Phase<0>{});
+    stage_a(1, Phase<1>{});
+    stage_a(2, Phase<2>{});
+    stage_a(3, Phase<3>{});
+    stage_a(4, Phase<4>{});
+    // B's carried y slope at row k0-1, from stage-1 rows k0-2 .. k0 (slots
+    // 0 .. 2), in the slot its first iteration (phase 5) reads.
+    {
+        const R a = R(wyo[0]), b = R(wyo[1]), c = R(wyo[2]);
+        slB[0] = limited_slope<LK>(a, b, c, theta);
+        ydmB = float(c - b);
+        ydmsB = LK == LK_SUPERBEE ? 2.0f * ydmB : float(theta) * ydmB;
+        hhB[0] = R(0);
+    }
+    auto body = [&](int it, auto phase) {
+        stage_a(it, phase);
+        stage_b(it, phase);
+    };
+    for (int it = 5;; it += 8) {
+        body(it, Phase<5>{});
         if (it + 1 > last) break;
-        body(it + 1, Phase<1>{});
+        body(it + 1, Phase<6>{});
         if (it + 2 > last) break;
-        body(it + 2, Phase<2>{});
+        body(it + 2, Phase<7>{});
         if (it + 3 > last) break;
-        body(it + 3, Phase<3>{});
+        body(it + 3, Phase<0>{});
         if (it + 4 > last) break;
-        body(it + 4, Phase<4>{});
+        body(it + 4, Phase<1>{});
         if (it + 5 > last) break;
-        body(it + 5, Phase<5>{});
+        body(it + 5, Phase<2>{});
         if (it + 6 > last) break;
-        body(it + 6, Phase<6>{});
+        body(it + 6, Phase<3>{});
         if (it + 7 > last) break;
-        body(it + 7, Phase<7>{});
+        body(it + 7, Phase<4>{});
         if (it + 8 > last) break;
     }
 }
