@@ -130,19 +130,47 @@ __global__ __launch_bounds__(kStatsBlocks) void stats_final_kernel(const StatsPa
     }
 }
 
-// Largest |v| per block (NaN if the block saw a non-finite value).
-__global__ __launch_bounds__(256) void absmax_kernel(const float *__restrict__ v, int64_t n,
-                                                     float *__restrict__ partial)
+// Largest |v| per block (NaN if the block saw a non-finite value).  Blocks
+// of 1024 threads (16 waves per CU) read four float4 each per trip, so
+// enough loads are in flight to stream the field at HBM rate; a misaligned
+// pointer or the last n % 4 values take the scalar loop.
+constexpr int kAbsmaxThreads = 1024;
+
+__global__ __launch_bounds__(kAbsmaxThreads) void absmax_kernel(const float *__restrict__ v, int64_t n,
+                                                                float *__restrict__ partial)
 {
-    __shared__ float lds[4];
+    __shared__ float lds[kAbsmaxThreads / 64];
     float m = 0.0f;
     bool bad = false;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const float x = v[i];
+    auto take = [&](float x) {
         bad |= !isfinite(x);
         m = fmaxf(m, fabsf(x));
+    };
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n4 = (reinterpret_cast<uintptr_t>(v) & 15) == 0 ? n / 4 : 0;
+    const float4 *__restrict__ v4 = reinterpret_cast<const float4 *>(v);
+    int64_t i = tid;
+    for (; i + 3 * nt < n4; i += 4 * nt) {
+        float4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = v4[i + u * nt];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            take(q[u].x);
+            take(q[u].y);
+            take(q[u].z);
+            take(q[u].w);
+        }
     }
+    for (; i < n4; i += nt) {
+        const float4 q = v4[i];
+        take(q.x);
+        take(q.y);
+        take(q.z);
+        take(q.w);
+    }
+    for (int64_t j = 4 * n4 + tid; j < n; j += nt) take(v[j]);
     if (bad) m = __builtin_nanf("");
     for (int o = 32; o > 0; o >>= 1) {
         const float other = __shfl_xor(m, o, 64);
@@ -152,7 +180,8 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float *__restrict__ v
     __syncthreads();
     if (threadIdx.x == 0) {
         float r = lds[0];
-        for (int w = 1; w < 4; ++w) r = (isnan(r) || isnan(lds[w])) ? __builtin_nanf("") : fmaxf(r, lds[w]);
+        for (int w = 1; w < kAbsmaxThreads / 64; ++w)
+            r = (isnan(r) || isnan(lds[w])) ? __builtin_nanf("") : fmaxf(r, lds[w]);
         partial[blockIdx.x] = r;
     }
 }
@@ -234,7 +263,7 @@ hipError_t launch_coupled_slip(const double *hsum, int64_t tiles, int time_order
 
 hipError_t launch_absmax(const float *v, int64_t n, float *d_partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(absmax_kernel, dim3(kAbsmaxBlocks), dim3(256), 0, s, v, n, d_partial);
+    hipLaunchKernelGGL(absmax_kernel, dim3(kAbsmaxBlocks), dim3(kAbsmaxThreads), 0, s, v, n, d_partial);
     return hipGetLastError();
 }
 

@@ -661,6 +661,35 @@ def test_step_size_equals_oracle(fdm, oracle, case):
     assert dt == oracle.cfl_dt(P, kw["cfl"])
 
 
+@pytest.mark.parametrize("nx,ny,offset,where", [(37, 23, 0, "last"), (37, 23, 1, "last"), (64, 48, 1, "first"),
+                                                (64, 48, 0, "middle"), (257, 129, 3, "last"), (256, 64, 0, "last")])
+def test_field_max_reduction_layouts(fdm, oracle, nx, ny, offset, where):
+    """max |v0| of a celerity field is reduced on the device with vector
+    loads where the field is 16-byte aligned and a scalar loop for the rest:
+    fields whose size is not a multiple of four, or that start 4, 8 or 12
+    bytes past an aligned address, with the largest magnitude at the first,
+    a middle or the last node, give the oracle's CFL step bit for bit, and a
+    NaN at that node is refused."""
+    import torch
+    rng = np.random.default_rng(7 * nx + offset)
+    field = rng.uniform(-1.0, 1.0, (ny, nx)).astype(np.float32)
+    idx = {"first": 0, "middle": nx * ny // 2, "last": nx * ny - 1}[where]
+    field.flat[idx] = -3.5
+    buf = torch.zeros(nx * ny + 4, dtype=torch.float32, device="cuda:0")
+    view = buf[offset:offset + nx * ny].view(ny, nx)
+    assert view.data_ptr() % 16 == 4 * offset
+    view.copy_(torch.from_numpy(field))
+    ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, cfl=0.45, v0_field=view), keep=[buf])
+    dt = fdm.fdm_transport_dt(ctx)
+    fdm.fdm_destroy(ctx)
+    P = oracle.Problem(nx, ny, dx=1.0, dy=1.0, vkind="law", V=(0.0, 0.0), v0=field.astype(np.float64))
+    assert dt == oracle.cfl_dt(P, 0.45)
+    view.view(-1)[idx] = float("nan")
+    with pytest.raises(fdm.FdmError) as e:
+        fdm.fdm_transport_init(fdm.desc(nx, ny, cfl=0.45, v0_field=view), keep=[buf])
+    assert e.value.status == fdm.FDM_ERR_INVALID_ARG
+
+
 # ------------------------------------------------------ extreme aspect ratios
 
 def _long_bands(nx, ny, seed):
