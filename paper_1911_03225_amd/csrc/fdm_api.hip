@@ -69,6 +69,7 @@ struct fdm_ctx {
         fdm::CoupledDev *d_cd = nullptr;    // step scalars on the device
         fdm::CoupledDev *h_cd = nullptr;    // pinned mirror
         double eps13 = 0.0, sigma13 = 0.0, phi_mean = 0.0, vmax = 0.0;
+        bool no_graph = false;              // a chunk could not be captured as kernels only
     } cw;
     size_t elem = sizeof(float);            // bytes per state value
     int64_t tile_capacity = 0;              // entries of d_tile_inst
@@ -453,8 +454,9 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
     if (!w.h_cd) FDM_HIP(c, hipHostMalloc((void **)&w.h_cd, sizeof(fdm::CoupledDev), hipHostMallocDefault));
 
     // The step scalars live on the device: each step enqueues its kernels
-    // without waiting (the step size, mean slip and mean stress are computed
-    // by one-block kernels); the host reads them back once per chunk.
+    // without waiting (the step size by the stage kernels, the mean slip and
+    // stress by the next step's pack kernel or, at a chunk end, one block);
+    // the host reads them back once per chunk.
     const double h = std::min(d.dx, d.dy), mu = L.mu, frac = (double)q.h / (double)q.n3;
     FDM_HIP(c, hipStreamSynchronize(c->stream));   // the pinned mirror may feed an earlier copy
     std::memset(w.h_cd, 0, sizeof(fdm::CoupledDev));
@@ -468,38 +470,102 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
     w.sigma13 = w.h_cd->sigma_bar;
 
     I.v0f = w.v0;
-    I.coef = &w.d_cd->coef;
+    I.vpart = c->d_absmax;
+    I.nvpart = fdm::velocity_law_blocks(n);
+    I.cfl_h = d.cfl * h;
+    I.dt_max = L.dt_max;
+    const fdm::SlipArgs slip{w.d_cd, w.d_hsum, tiles, c->time_order, 0, L.strain_rate13, mu, frac, (double)n};
     const int stages = c->time_order == 1 ? 1 : 2;
     const bool mid = c->time_order == 3;
-    int32_t rec = 0;
-    for (int32_t step = 0; step < n_steps; ++step) {
-        // 1-2. stress of the current state, then the celerity field
-        fdm::StaticStatus ss =
-            wiggly ? fdm::static_plan_run_phi(w.plan, a11[0], a12[0], w.tau, w.phi, &w.d_cd->sigma_bar,
-                                              &w.d_cd->phi_mean, c->stream, err)
-                   : fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, &w.d_cd->sigma_bar, c->stream, err);
-        if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
-        ss = fdm::velocity_law(w.tau, w.phi, f64, w.v0, n, law, c->d_absmax, c->stream, err);
-        if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
-        // 3. adaptive step from the velocity law's max |v0| partials, on the device
-        FDM_HIP(c, fdm::launch_coupled_dt(c->d_absmax, fdm::velocity_law_blocks(n), w.d_cd, d.cfl * h, L.dt_max,
-                                          d.dx, d.dy, c->stream));
-        // 4. one transport step with v0 frozen, per-tile sums of Hhat
-        I.hsum = w.d_hsum;
-        FDM_HIP(c, fdm::launch_stage(I, mid ? fdm::MODE_MID1 : fdm::MODE_FWD, c->precision, c->stream));
-        if (stages == 2) {
-            I.hsum = w.d_hsum + tiles;
-            FDM_HIP(c, fdm::launch_stage(I, mid ? fdm::MODE_MID2 : fdm::MODE_HEUN2, c->precision, c->stream));
-        } else {
-            FDM_HIP(c, fdm::launch_copy(I.a11, I.w11, n, c->precision, c->stream));
-            FDM_HIP(c, fdm::launch_copy(I.a12, I.w12, n, c->precision, c->stream));
+
+    // One chunk of m steps on stream s.  Each step: (1) the previous step's
+    // mean slip and loading, run by the first kernel of (2) the stress solve
+    // of the current state; the celerity field; (3-4) one transport step with
+    // v0 frozen, its step derived by the stage kernels from the velocity
+    // law's max |v0| partials, and per-tile sums of Hhat.  (5) The chunk's
+    // last slip update runs in a kernel of its own, ahead of the host's
+    // read-back.  Only kernels: the chunk replays as a graph.
+    auto enqueue_chunk = [&](int32_t m, hipStream_t s) -> fdm_status {
+        InstDev J = I;
+        for (int32_t j = 0; j < m; ++j) {
+            const fdm::SlipArgs *ps = j > 0 ? &slip : nullptr;
+            fdm::StaticStatus ss =
+                wiggly ? fdm::static_plan_run_phi(w.plan, a11[0], a12[0], w.tau, w.phi, &w.d_cd->sigma_bar,
+                                                  &w.d_cd->phi_mean, ps, s, err)
+                       : fdm::static_plan_run(w.plan, a11[0], a12[0], w.tau, &w.d_cd->sigma_bar, ps, s, err);
+            if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
+            ss = fdm::velocity_law(w.tau, w.phi, f64, w.v0, n, law, c->d_absmax, s, err);
+            if (ss != fdm::StaticStatus::Ok) return static_fail(c, ss, err);
+            J.hsum = w.d_hsum;
+            J.coef_out = &w.d_cd->coef;
+            FDM_HIP(c, fdm::launch_stage(J, mid ? fdm::MODE_MID1 : fdm::MODE_FWD, c->precision, s));
+            J.coef_out = nullptr;
+            if (stages == 2) {
+                J.hsum = w.d_hsum + tiles;
+                FDM_HIP(c, fdm::launch_stage(J, mid ? fdm::MODE_MID2 : fdm::MODE_HEUN2, c->precision, s));
+            } else {
+                FDM_HIP(c, fdm::launch_copy(J.a11, J.w11, n, c->precision, s));
+                FDM_HIP(c, fdm::launch_copy(J.a12, J.w12, n, c->precision, s));
+            }
         }
-        // 5. mean slip and loading
-        FDM_HIP(c, fdm::launch_coupled_slip(w.d_hsum, tiles, c->time_order, w.d_cd, L.strain_rate13, mu, frac,
-                                            (double)n, c->stream));
-        c->steps += 1;
-        const bool chunk_end = (step + 1) % chunk == 0 || step + 1 == n_steps;
-        if (!chunk_end) continue;
+        FDM_HIP(c, fdm::launch_coupled_slip(slip, s));
+        return FDM_OK;
+    };
+
+    // Full chunks replay one captured graph (kernel nodes only; a capture
+    // that fails or records anything else leaves the chunks enqueued one
+    // kernel at a time, with the same kernels).
+    hipGraphExec_t gexec = nullptr;
+    if (n_steps >= chunk && !w.no_graph) {
+        FDM_HIP(c, hipStreamSynchronize(c->stream));
+        const bool sticky0 = c->sticky;
+        const std::string err0 = c->err;
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const fdm_status cs = enqueue_chunk(chunk, c->capture);
+            ok = hipStreamEndCapture(c->capture, &g) == hipSuccess && cs == FDM_OK && g != nullptr;
+        }
+        size_t nn = 0;
+        if (ok) ok = hipGraphGetNodes(g, nullptr, &nn) == hipSuccess;
+        if (ok) {
+            std::vector<hipGraphNode_t> nodes(nn);
+            ok = hipGraphGetNodes(g, nodes.data(), &nn) == hipSuccess;
+            for (size_t k = 0; ok && k < nn; ++k) {
+                hipGraphNodeType t;
+                ok = hipGraphNodeGetType(nodes[k], &t) == hipSuccess && t == hipGraphNodeTypeKernel;
+            }
+        }
+        if (ok) ok = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+            if (gexec) (void)hipGraphExecDestroy(gexec);
+            gexec = nullptr;
+            w.no_graph = true;
+            (void)hipGetLastError();
+            c->sticky = sticky0;
+            c->err = err0;
+        }
+    }
+    struct GraphGuard {
+        hipGraphExec_t &g;
+        ~GraphGuard()
+        {
+            if (g) (void)hipGraphExecDestroy(g);
+        }
+    } guard{gexec};
+
+    int32_t rec = 0;
+    for (int32_t done = 0; done < n_steps;) {
+        const int32_t m = std::min(chunk, n_steps - done);
+        if (m == chunk && gexec) {
+            FDM_HIP(c, hipGraphLaunch(gexec, c->stream));
+        } else {
+            st = enqueue_chunk(m, c->stream);
+            if (st != FDM_OK) return st;
+        }
+        done += m;
+        c->steps += m;
         FDM_HIP(c, hipMemcpyAsync(w.h_cd, w.d_cd, sizeof(fdm::CoupledDev), hipMemcpyDeviceToHost, c->stream));
         FDM_HIP(c, hipStreamSynchronize(c->stream));
         if (w.h_cd->coef.nonfinite) return fail(c, FDM_ERR_NONFINITE, "non-finite celerity in the coupled run");
@@ -707,7 +773,8 @@ fdm_status fdm_static_solve(const fdm_static_desc *desc, const void *alpha11, co
             st = fdm::StaticStatus::Device;
             err = std::string("hipMemcpyAsync: ") + hipGetErrorString(ce);
         } else {
-            st = fdm::static_plan_run(plan, alpha11, alpha12, tau13_out, fdm::static_plan_scalars(plan), s, err);
+            st = fdm::static_plan_run(plan, alpha11, alpha12, tau13_out, fdm::static_plan_scalars(plan), nullptr, s,
+                                      err);
         }
         const hipError_t e = hipStreamSynchronize(s);
         if (st == fdm::StaticStatus::Ok && e != hipSuccess) {

@@ -50,17 +50,21 @@ struct StepCoef {
 // The step of a coupled run from the block partials of max |v0| (a NaN
 // partial marks a non-finite celerity): the largest float not above
 // min(cfl_h / max|v0|, dt_max) (dt_max when nothing moves) and the stage
-// coefficients.  Evaluated by one whole wave.
-__device__ __forceinline__ StepCoef step_coef_from_partials(const float *partial, int np, double cfl_h,
-                                                            double dt_max, double dx, double dy)
+// coefficients.  Evaluated by one whole wave, in two parts so that callers
+// can put other loads in flight beside the partials': x holds the lane's
+// partials lane + 64 j (0 where j indexes past the np <= kMaxPartials
+// partials).
+constexpr int kMaxPartials = 1024;
+
+__device__ __forceinline__ StepCoef step_coef_from_loaded(const float (&x)[kMaxPartials / 64], double cfl_h,
+                                                          double dt_max, double dx, double dy)
 {
-    const int lane = threadIdx.x & 63;
     float m = 0.0f;
     int bad = 0;
-    for (int i = lane; i < np; i += 64) {
-        const float x = partial[i];
-        bad |= __builtin_isnan(x) ? 1 : 0;
-        m = fmaxf(m, x);
+#pragma unroll
+    for (int j = 0; j < kMaxPartials / 64; ++j) {
+        bad |= __builtin_isnan(x[j]) ? 1 : 0;
+        m = fmaxf(m, x[j]);
     }
     for (int o = 32; o > 0; o >>= 1) {
         m = fmaxf(m, __shfl_xor(m, o, 64));
@@ -88,6 +92,81 @@ struct CoupledDev {
     double eps13, phi_mean, t, sigma_bar;
 };
 
+// The mean-slip update that ends a coupled step: from the per-tile sums of
+// Hhat of the step's stages, the mean slip, mean strain, time and mean
+// stress.
+struct SlipArgs {
+    CoupledDev *cd;
+    const double *hsum;   // first stage's tile sums, then the second's
+    int64_t tiles;
+    int32_t time_order, pad;
+    double rate, mu, frac, n_nodes;   // strain rate, shear modulus, h / L3, nodes
+};
+
+// Fixed-order compensated sums of u[0..n) and v[0..n) (v may be null: 0)
+// by one block of 256 threads: thread t adds elements t, t + 256, ... in
+// index order, then a pairwise tree over the threads.
+__device__ __forceinline__ void block_sums256(const double *u, const double *v, int64_t n, double2 *lds,
+                                              double &su, double &sv)
+{
+    double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+    auto add = [&](int k, double x) {
+        const double t = s[k] + x;
+        c[k] += fabs(s[k]) >= fabs(x) ? (s[k] - t) + x : (x - t) + s[k];
+        s[k] = t;
+    };
+    for (int64_t base = threadIdx.x; base < n; base += 256 * 4) {
+        double x[4], y[4];   // the loads first, then the sums in index order
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool in = base + 256 * q < n;
+            x[q] = in ? u[base + 256 * q] : 0.0;
+            y[q] = in && v ? v[base + 256 * q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (base + 256 * q >= n) break;
+            add(0, x[q]);
+            add(1, y[q]);
+        }
+    }
+    lds[threadIdx.x] = make_double2(s[0] + c[0], s[1] + c[1]);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            lds[threadIdx.x].x += lds[threadIdx.x + w].x;
+            lds[threadIdx.x].y += lds[threadIdx.x + w].y;
+        }
+        __syncthreads();
+    }
+    su = lds[0].x;
+    sv = lds[0].y;
+    __syncthreads();
+}
+
+// The slip update by one whole block of 256 threads (no contraction into
+// fused multiply-adds, whichever kernel runs it).
+__device__ __forceinline__ void coupled_slip_block(const SlipArgs &a, double2 *lds)
+{
+#pragma clang fp contract(off)
+    double s1, s2;
+    block_sums256(a.hsum, a.time_order == 1 ? nullptr : a.hsum + a.tiles, a.tiles, lds, s1, s2);
+    if (threadIdx.x == 0) {
+        // Euler: Hhat of the state; Heun: mean of the two stages; midpoint: the half-step state
+        CoupledDev *cd = a.cd;
+        double hmean = s1 / a.n_nodes;
+        if (a.time_order == 2) hmean = 0.5 * (hmean + s2 / a.n_nodes);
+        if (a.time_order == 3) hmean = s2 / a.n_nodes;
+        const double dt = (double)cd->coef.dt;
+        const double phi = cd->phi_mean - dt * hmean;
+        const double eps = cd->eps13 + a.rate * dt;
+        cd->phi_mean = phi;
+        cd->eps13 = eps;
+        cd->t = cd->t + dt;
+        cd->sigma_bar = 2.0 * a.mu * eps - a.mu * a.frac * phi;
+    }
+}
+
 // Device view of one transport instance.
 struct InstDev {
     void *a11, *a12;         // state, caller-owned (float, or double in PREC_FP64)
@@ -105,7 +184,14 @@ struct InstDev {
     double cxd, cyd, thetad; // the same coefficients for FP64 arithmetic
     double dtd, dxd, dyd;    // step and spacings (FP64 update in definition form)
     double *hsum;            // per-tile sums of Hhat (coupled runs) or nullptr
-    const StepCoef *coef;    // device step coefficients (coupled runs) or nullptr
+    // Coupled runs: the step comes from the velocity law's max |v0|
+    // partials, reduced by every wave of the stage kernels (so no launch
+    // stands between the law and the first stage); the wave of tile 0 of
+    // the first stage stores it in coef_out for the slip update and the host.
+    const float *vpart;      // the partials, or nullptr (the step in this struct)
+    StepCoef *coef_out;      // or nullptr
+    int32_t nvpart, pad2;
+    double cfl_h, dt_max;    // cfl min(dx, dy), the largest step
 };
 
 // Per-block partial of the diagnostics reduction (compensated sums).
@@ -135,12 +221,9 @@ hipError_t launch_copy(void *dst, const void *src, int64_t n, int precision, hip
 
 constexpr int kAbsmaxBlocks = 256;
 
-// Coupled runs: the step from the velocity law's max |v0| partials (one
-// wave), and, after the stages, the mean slip, mean strain, time and mean
-// stress from the per-tile sums of Hhat (one block).
-hipError_t launch_coupled_dt(const float *law_partials, int np, CoupledDev *cd, double cfl_h, double dt_max,
-                             double dx, double dy, hipStream_t s);
-hipError_t launch_coupled_slip(const double *hsum, int64_t tiles, int time_order, CoupledDev *cd, double rate,
-                               double mu, double frac, double n_nodes, hipStream_t s);
+// Coupled runs: the slip update of the last step before the host reads the
+// scalars back (one block; within a chunk the next step's pack kernel runs
+// it).
+hipError_t launch_coupled_slip(const SlipArgs &a, hipStream_t s);
 
 }  // namespace fdm

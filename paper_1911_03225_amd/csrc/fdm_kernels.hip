@@ -193,71 +193,18 @@ __global__ __launch_bounds__(256) void copy_kernel(S *__restrict__ dst, const S 
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
-// One wave: step coefficients from the max |v0| partials.
-__global__ __launch_bounds__(64) void coupled_dt_kernel(const float *__restrict__ partial, int np, CoupledDev *cd,
-                                                        double cfl_h, double dt_max, double dx, double dy)
+// One block: the slip update of a coupled step.
+__global__ __launch_bounds__(256) void coupled_slip_kernel(SlipArgs a)
 {
-    const StepCoef c = step_coef_from_partials(partial, np, cfl_h, dt_max, dx, dy);
-    if (threadIdx.x == 0) cd->coef = c;
-}
-
-// Fixed-order compensated sum of v[0..n) by one block of 256 threads.
-__device__ double block_sum(const double *__restrict__ v, int64_t n, double *lds)
-{
-    double s = 0.0, c = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        const double x = v[i], t = s + x;
-        c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-        s = t;
-    }
-    lds[threadIdx.x] = s + c;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = lds[0];
-    __syncthreads();
-    return r;
-}
-
-// One block: mean slip, mean strain, time and mean stress after a step.
-__global__ __launch_bounds__(256) void coupled_slip_kernel(const double *__restrict__ hsum, int64_t tiles,
-                                                           int time_order, CoupledDev *cd, double rate, double mu,
-                                                           double frac, double n_nodes)
-{
-    __shared__ double lds[256];
-    const double s1 = block_sum(hsum, tiles, lds);
-    const double s2 = time_order == 1 ? 0.0 : block_sum(hsum + tiles, tiles, lds);
-    if (threadIdx.x == 0) {
-        // Euler: Hhat of the state; Heun: mean of the two stages; midpoint: the half-step state
-        double hmean = s1 / n_nodes;
-        if (time_order == 2) hmean = 0.5 * (hmean + s2 / n_nodes);
-        if (time_order == 3) hmean = s2 / n_nodes;
-        const double dt = (double)cd->coef.dt;
-        const double phi = cd->phi_mean - dt * hmean;
-        const double eps = cd->eps13 + rate * dt;
-        cd->phi_mean = phi;
-        cd->eps13 = eps;
-        cd->t = cd->t + dt;
-        cd->sigma_bar = 2.0 * mu * eps - mu * frac * phi;
-    }
+    __shared__ double2 lds[256];
+    coupled_slip_block(a, lds);
 }
 
 }  // namespace
 
-hipError_t launch_coupled_dt(const float *law_partials, int np, CoupledDev *cd, double cfl_h, double dt_max,
-                             double dx, double dy, hipStream_t s)
+hipError_t launch_coupled_slip(const SlipArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(coupled_dt_kernel, dim3(1), dim3(64), 0, s, law_partials, np, cd, cfl_h, dt_max, dx, dy);
-    return hipGetLastError();
-}
-
-hipError_t launch_coupled_slip(const double *hsum, int64_t tiles, int time_order, CoupledDev *cd, double rate,
-                               double mu, double frac, double n_nodes, hipStream_t s)
-{
-    hipLaunchKernelGGL(coupled_slip_kernel, dim3(1), dim3(256), 0, s, hsum, tiles, time_order, cd, rate, mu, frac,
-                       n_nodes);
+    hipLaunchKernelGGL(coupled_slip_kernel, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

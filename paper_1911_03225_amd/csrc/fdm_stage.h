@@ -536,16 +536,29 @@ constexpr int kAhead = 2;
 // The first midpoint stage runs the MODE_FWD kernel with half the step:
 // halving is exact in float and double, so the coefficients are those of
 // dt/2.
-// Coupled runs: the step is chosen on the device, so the coefficients come
-// from device memory (one scalar load each, once per wave).
-__device__ __forceinline__ void load_coef(InstDev &I)
+// Coupled runs: the step is chosen on the device, from the velocity law's
+// max |v0| partials (each wave loads them first, beside its first rows, and
+// reduces them: a few kilobytes from L2).
+// The partials this lane reduces (zeros, with no memory read, when the
+// instance has none).
+__device__ __forceinline__ void load_partials(const InstDev &I, float (&x)[kMaxPartials / 64])
 {
-    if (I.coef == nullptr) return;
-    I.dtd = I.coef->dtd;
-    I.cxd = I.coef->cxd;
-    I.cyd = I.coef->cyd;
-    I.cx = I.coef->cx;
-    I.cy = I.coef->cy;
+    const int lane = threadIdx.x & 63;
+    const auto row = row_ptr<float>(I.vpart, 0, I.nvpart, I.vpart != nullptr);
+#pragma unroll
+    for (int j = 0; j < kMaxPartials / 64; ++j) x[j] = at(row, (uint32_t)(lane + 64 * j) * 4u);
+}
+
+__device__ __forceinline__ void load_coef(InstDev &I, bool tile0, const float (&x)[kMaxPartials / 64])
+{
+    if (I.vpart == nullptr) return;
+    const StepCoef c = step_coef_from_loaded(x, I.cfl_h, I.dt_max, I.dxd, I.dyd);
+    I.dtd = c.dtd;
+    I.cxd = c.cxd;
+    I.cyd = c.cyd;
+    I.cx = c.cx;
+    I.cy = c.cy;
+    if (tile0 && I.coef_out != nullptr && (threadIdx.x & 63) == 0) *I.coef_out = c;
 }
 
 __device__ __forceinline__ void halve_step(InstDev &I)
@@ -595,6 +608,8 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
         v0_[j] = 0.0f;
         b12_[j] = b11_[j] = S(0);
     }
+    float vpart[kMaxPartials / 64];   // coupled runs (HSUM): the step's inputs, first in flight
+    if constexpr (HSUM) load_partials(I, vpart);
     int k = (k0 - 2) % ny;
     if (k < 0) k += ny;
     const R ym2 = R(at(row_ptr<S>(s11, k, nx), off));
@@ -630,7 +645,7 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
 
     // The step coefficients, with the first loads already in flight (coupled
     // runs read them from device memory).
-    load_coef(I);
+    if constexpr (HSUM) load_coef(I, strip == 0 && chunk == 0, vpart);
     if (half) halve_step(I);
     const R cx = kF64 ? R(I.cxd) : R(I.cx);
     const R cy = kF64 ? R(I.cyd) : R(I.cy);

@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <string>
 
+#include "fdm_internal.h"
+
 namespace fdm {
 
 enum class StaticStatus { Ok, Device, OutOfMemory };
@@ -26,14 +28,17 @@ void static_plan_destroy(StaticPlan *p);
 
 // Enqueues tau13 = layer average of sigma13 for densities (a11, a12) and
 // the mean stress *sigma_bar (a device double, read when the kernel runs)
-// on s.  a11/a12 are read only; tau13 is written.
+// on s.  a11/a12 are read only; tau13 is written.  slip (may be null): a
+// coupled step's pending slip update, run by the first kernel (before
+// anything reads the mean stress or slip).
 StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, const double *sigma_bar,
-                             hipStream_t s, std::string &err);
+                             const SlipArgs *slip, hipStream_t s, std::string &err);
 
 // As static_plan_run, and also phi (= U^p_13) at the nodes with the mean
 // *phi_mean (a device double), from the same forward transforms.
 StaticStatus static_plan_run_phi(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
-                                 const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err);
+                                 const double *sigma_bar, const double *phi_mean, const SlipArgs *slip,
+                                 hipStream_t s, std::string &err);
 
 // Two device doubles owned by the plan, for callers that hold the mean
 // stress and slip on the host (upload them before a run).

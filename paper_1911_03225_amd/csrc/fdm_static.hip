@@ -92,12 +92,18 @@ __global__ __launch_bounds__(256) void green_kernel(const T *spec, T *out, const
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void pack_kernel(T *dst, const T *a11, const T *a12, int64_t n)
+__global__ __launch_bounds__(256) void pack_kernel(T *dst, const T *a11, const T *a12, int64_t n, SlipArgs slip)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         dst[i] = a11[i];
         dst[n + i] = a12[i];
+    }
+    // the previous coupled step's slip update, ahead of every reader of the
+    // mean stress and slip (the later kernels of this solve)
+    if (slip.cd != nullptr && blockIdx.x == 0) {
+        __shared__ double2 lds[256];
+        coupled_slip_block(slip, lds);
     }
 }
 
@@ -351,37 +357,42 @@ StaticStatus static_plan_create(const StaticParams &q, hipStream_t s, StaticPlan
 
 namespace {
 StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
-                      const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err);
+                      const double *sigma_bar, const double *phi_mean, const SlipArgs *slip, hipStream_t s,
+                      std::string &err);
 }
 
 double *static_plan_scalars(StaticPlan *p) { return p->scal; }
 
 StaticStatus static_plan_run(StaticPlan *p, const void *a11, const void *a12, void *tau13, const double *sigma_bar,
-                             hipStream_t s, std::string &err)
+                             const SlipArgs *slip, hipStream_t s, std::string &err)
 {
-    return run_impl(p, a11, a12, tau13, nullptr, sigma_bar, nullptr, s, err);
+    return run_impl(p, a11, a12, tau13, nullptr, sigma_bar, nullptr, slip, s, err);
 }
 
 StaticStatus static_plan_run_phi(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
-                                 const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err)
+                                 const double *sigma_bar, const double *phi_mean, const SlipArgs *slip,
+                                 hipStream_t s, std::string &err)
 {
-    return run_impl(p, a11, a12, tau13, phi, sigma_bar, phi_mean, s, err);
+    return run_impl(p, a11, a12, tau13, phi, sigma_bar, phi_mean, slip, s, err);
 }
 
 namespace {
 StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau13, void *phi,
-                      const double *sigma_bar, const double *phi_mean, hipStream_t s, std::string &err)
+                      const double *sigma_bar, const double *phi_mean, const SlipArgs *slip, hipStream_t s,
+                      std::string &err)
 {
+    SlipArgs sa{};
+    if (slip) sa = *slip;
     const int64_t n = (int64_t)p->nx * p->ny, nm = (int64_t)p->nxh * p->ny;
     ST_FFT(rocfft_execution_info_set_stream(p->info, s));
     const unsigned pb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
     const unsigned gb = (unsigned)((nm + 255) / 256);
     if (p->f64) {
         hipLaunchKernelGGL(pack_kernel<double>, dim3(pb), dim3(256), 0, s, (double *)p->real2, (const double *)a11,
-                           (const double *)a12, n);
+                           (const double *)a12, n, sa);
     } else {
         hipLaunchKernelGGL(pack_kernel<float>, dim3(pb), dim3(256), 0, s, (float *)p->real2, (const float *)a11,
-                           (const float *)a12, n);
+                           (const float *)a12, n, sa);
     }
     ST_HIP(hipGetLastError());
     void *in[1] = {p->real2}, *outb[1] = {p->spec};
@@ -419,6 +430,7 @@ StaticStatus run_impl(StaticPlan *p, const void *a11, const void *a12, void *tau
 }
 }  // namespace
 
+static_assert(kLawBlocks <= kMaxPartials, "the stage kernels reduce at most kMaxPartials partials");
 int velocity_law_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, kLawBlocks); }
 
 StaticStatus velocity_law(const void *tau13, const void *phi, bool f64, float *v0, int64_t n, const LawParams &L,
