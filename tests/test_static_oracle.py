@@ -57,7 +57,9 @@ def test_full_thickness_band_along_x2_is_stress_free():
 
 
 @pytest.mark.parametrize("nx,ny,h,n3,mu,lam,d", [(10, 8, 2, 6, 1.0, 1.5, 1.0), (8, 12, 3, 8, 0.7, 0.4, 1.0),
-                                                 (9, 7, 1, 5, 1.0, 3.0, 1.0), (8, 6, 2, 7, 1.0, 1.5, 0.35)])
+                                                 (9, 7, 1, 5, 1.0, 3.0, 1.0), (8, 6, 2, 7, 1.0, 1.5, 0.35),
+                                                 # thin layers, as in the coupled workload (4 of 512 voxels)
+                                                 (32, 32, 4, 64, 1.0, 1.5, 1.0), (24, 20, 2, 128, 1.0, 1.5, 1.0)])
 def test_layer_multiplier_matches_3d_green_operator(nx, ny, h, n3, mu, lam, d):
     phi = _smooth_phi(nx, ny, nx * ny) + np.random.default_rng(3).normal(0, 0.02, (ny, nx))
     a11, a12 = _alpha(phi, d, d)
