@@ -43,6 +43,9 @@ FIELD_BYTES = 4
 PROFILE_FILE = os.path.join(ROOT, "profiles", "fused_kernel_bands_field_4096_fp32_counters.json")
 KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_kernels.hip"]
 HEADLINE_KERNEL = "fused_kernel<3, 0, true, false>"   # minmod, LAW, celerity field, Heun
+# Repeated autotuner runs on one box order heights within about 3% of each
+# other differently; within that the height the counters were taken at is kept.
+PROFILED_HEIGHT_SLACK = 1.03
 COPY_KERNEL = "copy_kernel<float>"
 GOLDEN_C4 = os.path.join(ROOT, "tests", "golden", "coupled_c4_history.json")
 
@@ -151,7 +154,7 @@ def single_instance(fdm, a11, a12, K, W, repeats, stream, desc_kw, options, auto
     """Autotune, a K-step run from the inputs (kept for parity), W warmup
     steps, then the timed K-step repeats.  Returns timing and the state
     after the first K steps.  prefer_rows: a fused tile height to keep when
-    the autotuner timed it within 1% of its best (the height the counter
+    the autotuner timed it within 3% of its best (the height the counter
     passes were taken at)."""
     import numpy as np
     import torch
@@ -170,13 +173,13 @@ def single_instance(fdm, a11, a12, K, W, repeats, stream, desc_kw, options, auto
         best = min(trials, key=lambda t: t["seconds_per_step"])
         sched, choice = best["schedule"], "autotuned"
         near = [t for t in trials if t["schedule"] == "fused" and t["tile_rows"] == prefer_rows and
-                t["seconds_per_step"] <= 1.01 * best["seconds_per_step"]]
+                t["seconds_per_step"] <= PROFILED_HEIGHT_SLACK * best["seconds_per_step"]]
         if near and (best["schedule"], best["tile_rows"]) != ("fused", prefer_rows):
             fdm.fdm_destroy(ctx)
             ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, v0_field=field, **desc_kw),
                                          options=dict(options, schedule="fused", tile_rows=prefer_rows),
                                          stream=stream, keep=[field] if field is not None else [])
-            sched, choice = "fused", "profiled height, within 1% of the autotuned best"
+            sched, choice = "fused", "profiled height, within 3% of the autotuned best"
     rows = fdm.fdm_tile_rows(ctx, 0)
     dt = fdm.fdm_transport_dt(ctx)
     fdm.fdm_transport_step(ctx, t11, t12, K)        # from the inputs: the result the oracle checks

@@ -363,7 +363,8 @@ int32_t fdm_tile_rows(const fdm_ctx *ctx, int32_t instance);
 typedef struct fdm_tune_trial {
     int32_t tile_rows;       /* rows per wave tile tried (all instances)        */
     int32_t schedule;        /* FDM_SCHEDULE_BATCHED, _PLAIN or _FUSED          */
-    double seconds_per_step; /* faster of two timed runs of trial_steps steps   */
+    double seconds_per_step; /* fastest timed run of trial_steps steps (two;
+                                five for the three fastest candidates)        */
 } fdm_tune_trial;
 
 /* Autotuner for the launch shape (not a step of the paper's method: tiling
@@ -376,8 +377,9 @@ typedef struct fdm_tune_trial {
  * so that the SIMDs carry equal work; and, for a context created with
  * FDM_SCHEDULE_AUTO,
  * for each schedule that applies: batched and plain (several instances),
- * and fused (FP32 precision, time_order 2 or 3, semi-discrete scheme).  The
- * context then keeps the fastest candidate.  alpha11/alpha12 are read, never
+ * and fused (FP32 precision, time_order 2 or 3, semi-discrete scheme).  Each
+ * candidate is timed twice; the three fastest are then timed three more
+ * times each, interleaved, and the context keeps the fastest of them.  alpha11/alpha12 are read, never
  * written; the step count and diagnostics baseline are unchanged.  Up to
  * max_trials measured candidates are written to trials (may be NULL when
  * max_trials is 0) and their number to *n_trials (may be NULL).  Synchronous:

@@ -898,6 +898,39 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
         schedules = {was_fused ? FDM_SCHEDULE_FUSED : was_batched ? FDM_SCHEDULE_BATCHED : FDM_SCHEDULE_PLAIN};
     }
 
+    // Seconds per step of one launch shape on the scratch state: a warm-up
+    // step, then the fastest of `reps` timed runs of trial_steps steps.
+    auto time_shape = [&](int rows, bool batched, bool fused, int reps, double *out) -> fdm_status {
+        c->batched = batched;
+        c->fused = fused;
+        fdm_status r = retile(c, rows);
+        if (r != FDM_OK) return r;
+        r = bind(c, s11.data(), s12.data());
+        if (r != FDM_OK) return r;
+        r = enqueue_steps(c, 1, c->stream);
+        if (r != FDM_OK) return r;
+        double best_t = 0.0;
+        for (int k = 0; k < reps; ++k) {
+            FDM_HIP(c, hipEventRecord(e0, c->stream));
+            r = enqueue_steps(c, trial_steps, c->stream);
+            if (r != FDM_OK) return r;
+            FDM_HIP(c, hipEventRecord(e1, c->stream));
+            FDM_HIP(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            FDM_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+            const double t = 1e-3 * ms / trial_steps;
+            if (k == 0 || t < best_t) best_t = t;
+        }
+        *out = best_t;
+        return FDM_OK;
+    };
+    struct Cand {
+        int rows, sched;
+        bool batched, fused;
+        double sec;
+        int32_t slot;   // its entry in trials, or -1
+    };
+    std::vector<Cand> cands;
     auto run = [&]() -> fdm_status {
         int64_t off = 0;
         for (int i = 0; i < c->n; ++i) {
@@ -928,40 +961,38 @@ fdm_status fdm_autotune(fdm_ctx *c, void *const *alpha11, void *const *alpha12, 
                     heights.push_back(rows);
             }
             for (int rows : heights) {
-                c->batched = batched;
-                c->fused = fused;
-                fdm_status r = retile(c, rows);
+                double sec = 0.0;
+                fdm_status r = time_shape(rows, batched, fused, 2, &sec);
                 if (r != FDM_OK) return r;
-                r = bind(c, s11.data(), s12.data());
-                if (r != FDM_OK) return r;
-                r = enqueue_steps(c, 1, c->stream);   // warm-up
-                if (r != FDM_OK) return r;
-                double t[2];
-                for (double &ti : t) {
-                    FDM_HIP(c, hipEventRecord(e0, c->stream));
-                    r = enqueue_steps(c, trial_steps, c->stream);
-                    if (r != FDM_OK) return r;
-                    FDM_HIP(c, hipEventRecord(e1, c->stream));
-                    FDM_HIP(c, hipEventSynchronize(e1));
-                    float ms = 0.0f;
-                    FDM_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-                    ti = 1e-3 * ms / trial_steps;
-                }
-                const double sec = std::min(t[0], t[1]);
                 if (count < max_trials) {
                     trials[count].tile_rows = rows;
                     trials[count].schedule = sched;
                     trials[count].seconds_per_step = sec;
                 }
+                cands.push_back({rows, sched, batched, fused, sec, count < max_trials ? count : -1});
                 ++count;
-                if (best_rows < 0 || sec < best) {
-                    best = sec;
-                    best_rows = rows;
-                    best_batched = batched;
-                    best_fused = fused;
-                }
             }
         }
+        // Confirmation: candidates a few percent apart in one timing can
+        // swap places in the next, so the three fastest are timed again,
+        // interleaved, three more times each, and keep their fastest time.
+        std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.sec < b.sec; });
+        const size_t top = std::min<size_t>(3, cands.size());
+        for (int round = 0; round < 3 && top > 1; ++round)
+            for (size_t k = 0; k < top; ++k) {
+                double sec = 0.0;
+                fdm_status r = time_shape(cands[k].rows, cands[k].batched, cands[k].fused, 1, &sec);
+                if (r != FDM_OK) return r;
+                cands[k].sec = std::min(cands[k].sec, sec);
+                if (cands[k].slot >= 0) trials[cands[k].slot].seconds_per_step = cands[k].sec;
+            }
+        for (size_t k = 0; k < top; ++k)
+            if (best_rows < 0 || cands[k].sec < best) {
+                best = cands[k].sec;
+                best_rows = cands[k].rows;
+                best_batched = cands[k].batched;
+                best_fused = cands[k].fused;
+            }
         return FDM_OK;
     };
     st = run();
