@@ -341,9 +341,10 @@ typedef struct fdm_loading {
  * descriptor) and dx == dy; the descriptor's v0 / v0_field are not used
  * during the run (they are again after it).  The step size, mean slip and
  * mean stress are computed on the device, so steps are enqueued without
- * waiting; full chunks are replayed from a HIP graph captured once per call
- * (where the FFT library's launches can be captured as kernels; otherwise
- * the same kernels are enqueued directly), and the stream is synchronized
+ * waiting; with two full chunks or more, they are replayed from a HIP graph
+ * captured once per call (where the FFT library's launches can be captured
+ * as kernels; otherwise the same kernels are enqueued directly), and the
+ * stream is synchronized
  * once per chunk (to read those scalars back, and for the stats record).
  * Results do not depend on the chunk length.  The first call allocates the
  * coupled workspace (FFT plans, a stress and a celerity field, per-tile

@@ -512,11 +512,11 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
         return FDM_OK;
     };
 
-    // Full chunks replay one captured graph (kernel nodes only; a capture
-    // that fails or records anything else leaves the chunks enqueued one
-    // kernel at a time, with the same kernels).
+    // Full chunks replay one captured graph when there are at least two of
+    // them (kernel nodes only; a capture that fails or records anything else
+    // leaves the chunks enqueued one kernel at a time, with the same kernels).
     hipGraphExec_t gexec = nullptr;
-    if (n_steps >= chunk && !w.no_graph) {
+    if (n_steps / chunk >= 2 && !w.no_graph) {
         FDM_HIP(c, hipStreamSynchronize(c->stream));
         const bool sticky0 = c->sticky;
         const std::string err0 = c->err;

@@ -116,12 +116,13 @@ def test_coupled_fp32_follows_oracle(fdm):
 
 @pytest.mark.parametrize("precision,time_order", [("fp32", 2), ("fp64", 2), ("fp32", 1), ("fp32", 3)])
 def test_coupled_chunking_is_bitwise_neutral(fdm, precision, time_order):
-    """Full chunks of a coupled run replay one captured graph, a shorter
-    last chunk is enqueued kernel by kernel, and a step's slip update runs
-    in the next step's first kernel or, at a chunk end, in a kernel of its
-    own.  Thirty steps in chunks of 1000 (no graph), 30 (one replay), 7 (four
-    replays with diagnostics between them, then a two-step tail) and 1
-    (thirty replays) give the same state and scalars bit for bit."""
+    """With two full chunks or more a coupled run replays one captured graph
+    per chunk, a shorter last chunk is enqueued kernel by kernel, and a
+    step's slip update runs in the next step's first kernel or, at a chunk
+    end, in a kernel of its own.  Thirty steps in chunks of 1000 and 30 (no
+    graph), 7 (four replays with diagnostics between them, then a two-step
+    tail) and 1 (thirty replays) give the same state and scalars bit for
+    bit."""
     phi, a11, a12 = _case(seed=5, nx=72, ny=56)
     cfl = 0.25 if time_order == 1 else 0.4
     runs = {}
