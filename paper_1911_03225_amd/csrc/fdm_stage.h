@@ -111,6 +111,57 @@ template <> struct Arith<double> {
     }
 };
 
+// Two independent float evaluations in lock step: each operation applies
+// the scalar operation to both components, so results are those of two
+// scalar evaluations bit for bit, and the compiler sees the two instruction
+// streams interleaved (the fused kernel evaluates its two stages' nodes of
+// a row this way).
+struct F2 {
+    float a, b;
+    __host__ __device__ constexpr F2() : a(0.0f), b(0.0f) {}
+    __host__ __device__ constexpr F2(float v) : a(v), b(v) {}
+    __host__ __device__ constexpr F2(float x, float y) : a(x), b(y) {}
+};
+__device__ __forceinline__ F2 operator+(F2 x, F2 y) { return F2(x.a + y.a, x.b + y.b); }
+__device__ __forceinline__ F2 operator-(F2 x, F2 y) { return F2(x.a - y.a, x.b - y.b); }
+__device__ __forceinline__ F2 operator*(F2 x, F2 y) { return F2(x.a * y.a, x.b * y.b); }
+__device__ __forceinline__ F2 operator-(F2 x) { return F2(-x.a, -x.b); }
+__device__ __forceinline__ F2 vmin(F2 x, F2 y) { return F2(fminf(x.a, y.a), fminf(x.b, y.b)); }
+__device__ __forceinline__ F2 vmax(F2 x, F2 y) { return F2(fmaxf(x.a, y.a), fmaxf(x.b, y.b)); }
+__device__ __forceinline__ F2 madd(F2 x, F2 y, F2 z)
+{
+    return F2(__builtin_fmaf(x.a, y.a, z.a), __builtin_fmaf(x.b, y.b, z.b));
+}
+__device__ __forceinline__ F2 from_left(F2 v) { return F2(from_left(v.a), from_left(v.b)); }
+__device__ __forceinline__ F2 from_right(F2 v) { return F2(from_right(v.a), from_right(v.b)); }
+
+template <> struct Arith<F2> {
+    static constexpr F2 tiny = F2(Arith<float>::tiny);
+    static __device__ __forceinline__ F2 rsq(F2 r) { return F2(Arith<float>::rsq(r.a), Arith<float>::rsq(r.b)); }
+    static __device__ __forceinline__ F2 rcp(F2 x) { return F2(Arith<float>::rcp(x.a), Arith<float>::rcp(x.b)); }
+};
+
+// float arithmetic (one value or a lock-step pair)
+template <typename R> struct IsF32 {
+    static constexpr bool value = false;
+};
+template <> struct IsF32<float> {
+    static constexpr bool value = true;
+};
+template <> struct IsF32<F2> {
+    static constexpr bool value = true;
+};
+
+// The middle of three values; +-infinity with the sign of s; a when v > 0
+// else b (v is the same in both components of a pair).
+__device__ __forceinline__ float med3(float x, float y, float z) { return __builtin_amdgcn_fmed3f(x, y, z); }
+__device__ __forceinline__ F2 med3(F2 x, F2 y, F2 z) { return F2(med3(x.a, y.a, z.a), med3(x.b, y.b, z.b)); }
+__device__ __forceinline__ float sign_inf(float s) { return copysignf(__builtin_inff(), s); }
+__device__ __forceinline__ F2 sign_inf(F2 s) { return F2(sign_inf(s.a), sign_inf(s.b)); }
+__device__ __forceinline__ float pick_pos(float v, float a, float b) { return v > 0.0f ? a : b; }
+__device__ __forceinline__ double pick_pos(double v, double a, double b) { return v > 0.0 ? a : b; }
+__device__ __forceinline__ F2 pick_pos(F2 v, F2 a, F2 b) { return F2(pick_pos(v.a, a.a, b.a), pick_pos(v.b, a.b, b.b)); }
+
 // ---------------------------------------------------------------- Step 1
 
 // Limiter kinds compiled separately.  The minmod family shares one body with
@@ -158,16 +209,16 @@ __device__ __forceinline__ R limited_slope(R wm, R w0, R wp, R theta)
     if constexpr (LK == LK_NONE) {
         return R(0);
     } else if constexpr (LK == LK_MINMOD) {
-        static_assert(sizeof(R) == 4, "minmod has its own kind in float arithmetic only");
-        return __builtin_amdgcn_fmed3f(w0 - wm, wp - w0, 0.0f);
-    } else if constexpr (sizeof(R) == 4 && LK == LK_SUPERBEE) {
-        const float dm = w0 - wm, dp = wp - w0;
-        const float s1 = __builtin_amdgcn_fmed3f(2.0f * dm, dp, 0.0f);
-        const float s2 = __builtin_amdgcn_fmed3f(dm, 2.0f * dp, 0.0f);
-        return __builtin_amdgcn_fmed3f(s1, s2, copysignf(__builtin_inff(), dp));
-    } else if constexpr (sizeof(R) == 4) {
-        const float a = theta * (wp - w0), b = 0.5f * (wp - wm), c = theta * (w0 - wm);
-        return __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, c, 0.0f), b, 0.0f);
+        static_assert(IsF32<R>::value, "minmod has its own kind in float arithmetic only");
+        return med3(w0 - wm, wp - w0, R(0.0f));
+    } else if constexpr (IsF32<R>::value && LK == LK_SUPERBEE) {
+        const R dm = w0 - wm, dp = wp - w0;
+        const R s1 = med3(R(2.0f) * dm, dp, R(0.0f));
+        const R s2 = med3(dm, R(2.0f) * dp, R(0.0f));
+        return med3(s1, s2, sign_inf(dp));
+    } else if constexpr (IsF32<R>::value) {
+        const R a = theta * (wp - w0), b = R(0.5f) * (wp - wm), c = theta * (w0 - wm);
+        return med3(med3(a, c, R(0.0f)), b, R(0.0f));
     } else if constexpr (LK == LK_SUPERBEE) {
         const R dm = w0 - wm, dp = wp - w0;
         const R adm = vabs(dm), adp = vabs(dp);
@@ -187,26 +238,27 @@ __device__ __forceinline__ R limited_slope(R wm, R w0, R wp, R theta)
 // superbee, theta D for the minmod family).  Same results as limited_slope,
 // two instructions fewer.  dm, dms: in, the carried difference and its scaled
 // form; out, this row's.
-template <int LK>
-__device__ __forceinline__ float y_slope_carried(float wm, float w0, float wp, float theta, float &dm, float &dms)
+template <int LK, typename R>
+__device__ __forceinline__ R y_slope_carried(R wm, R w0, R wp, R theta, R &dm, R &dms)
 {
+    static_assert(IsF32<R>::value, "the carried y slope is a float path");
     if constexpr (LK == LK_NONE) {
-        return 0.0f;
+        return R(0.0f);
     } else {
-        const float dp = wp - w0;
-        float s, dps;
+        const R dp = wp - w0;
+        R s, dps;
         if constexpr (LK == LK_MINMOD) {
             dps = dp;
-            s = __builtin_amdgcn_fmed3f(dm, dp, 0.0f);
+            s = med3(dm, dp, R(0.0f));
         } else if constexpr (LK == LK_SUPERBEE) {
-            dps = 2.0f * dp;
-            const float s1 = __builtin_amdgcn_fmed3f(dms, dp, 0.0f);
-            const float s2 = __builtin_amdgcn_fmed3f(dm, dps, 0.0f);
-            s = __builtin_amdgcn_fmed3f(s1, s2, copysignf(__builtin_inff(), dp));
+            dps = R(2.0f) * dp;
+            const R s1 = med3(dms, dp, R(0.0f));
+            const R s2 = med3(dm, dps, R(0.0f));
+            s = med3(s1, s2, sign_inf(dp));
         } else {
             dps = theta * dp;
-            const float b = 0.5f * (wp - wm);
-            s = __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(dps, dms, 0.0f), b, 0.0f);
+            const R b = R(0.5f) * (wp - wm);
+            s = med3(med3(dps, dms, R(0.0f)), b, R(0.0f));
         }
         dm = dp;
         dms = dps;
@@ -221,8 +273,8 @@ __device__ __forceinline__ R numerical_hamiltonian(R pxm, R pxp, R pym, R pyp, R
 {
     if constexpr (VK == VK_PRESCRIBED) {
         // H = V.p: the central-upwind weights reduce to pure upwinding.
-        const R px = V1 > R(0) ? pxm : pxp;
-        const R py = V2 > R(0) ? pym : pyp;
+        const R px = pick_pos(V1, pxm, pxp);
+        const R py = pick_pos(V2, pym, pyp);
         return madd(V2, py, V1 * px);
     } else {
         // H = v0 |p| at the four corners (s,t) in {-,+}^2, dH/dp = v0 p/|p|.
@@ -845,59 +897,41 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
 
     // The node function of both stages: Steps 1-4 at one node from the
     // alpha_11 rows above/at/below and alpha_12 of the row, with the y slope
-    // carried from the previous row (as in run_tile).
-    auto node = [&](R ym1, R y0, R yp1, R wx, R v0, R *sl, int h, int hp, float &ydm, float &ydms) {
-        const R s0 = y_slope_carried<LK>(ym1, y0, yp1, theta, ydm, ydms);
-        const R pyp = -madd(R(-0.5), s0, y0);
-        const R pym = -madd(R(0.5), sl[hp], ym1);
-        sl[h] = s0;
-        const R wl = from_left(wx), wr = from_right(wx);
-        const R sx = limited_slope<LK>(wl, wx, wr, theta);
-        const R pxp = madd(R(-0.5), sx, wx);
-        const R pxm = from_left(madd(R(0.5), sx, wx));
-        return numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, V1, V2);
+    // carried from the previous row (as in run_tile); slhp is the slope of
+    // the row above, s0 receives this row's.  T is float (one node) or F2
+    // (the two stages' nodes of an iteration in lock step).
+    auto node = [&](auto ym1, auto y0, auto yp1, auto wx, auto v0, auto slhp, auto &s0, auto &ydm, auto &ydms) {
+        using T = decltype(ym1);
+        s0 = y_slope_carried<LK>(ym1, y0, yp1, T(theta), ydm, ydms);
+        const T pyp = -madd(T(-0.5f), s0, y0);
+        const T pym = -madd(T(0.5f), slhp, ym1);
+        const T wl = from_left(wx), wr = from_right(wx);
+        const T sx = limited_slope<LK>(wl, wx, wr, T(theta));
+        const T pxp = madd(T(-0.5f), sx, wx);
+        const T pxm = from_left(madd(T(0.5f), sx, wx));
+        return numerical_hamiltonian<VK>(pxm, pxp, pym, pyp, v0, T(V1), T(V2));
     };
 
-    // Stage A on iteration it (ring phase p = it & 7).
-    auto stage_a = [&](int it, auto phase) {
+    // A's outputs at ring phase p from its Hhat at row m and at the node to
+    // the right: alpha_12 of row m and alpha_11 of row m-1 after stage 1.
+    auto update_a = [&](auto phase, R hv, R hr, R wx, R ym1) {
         constexpr int p = decltype(phase)::value;
         constexpr int h = p & 1, hp = h ^ 1;
-        const R ym1 = R(y[(p + 7) & 7]), y0 = R(y[p]), yp1 = R(y[(p + 1) & 7]);
-        const R wx = R(wx_[p]);
-        const R v0 = FIELD ? R(v0_[p]) : R(I.v0);
-        b11_[(p + 3) & 3] = y[(p + 7) & 7];   // row m-1
-        b12_[p & 3] = wx_[p];                 // row m
-        if constexpr (FIELD) vb_[p & 3] = v0_[p];
-        {   // operands of A's row m + kFAhead (none past A's last useful row)
-            const bool live = it + kFAhead <= lastA;
-            wx_[(p + kFAhead) & 7] = at(row_ptr<S>(src12, kf, nx, live), off);
-            y[(p + kFAhead + 1) & 7] = at(row_ptr<S>(src11, kf1, nx, live), off);
-            if constexpr (FIELD) v0_[(p + kFAhead) & 7] = at(row_ptr<float>(I.v0f, kf, nx, live), off);
-            kf = kf1;
-            kf1 = next_row(kf1, ny);
-        }
-        const R hv = node(ym1, y0, yp1, wx, v0, slA, h, hp, ydmA, ydmsA);
-        const R hr = from_right(hv);
         const R hprev = hhA[hp];
         hhA[h] = hv;
-        wxo[p & 3] = S(madd(-cxa, hr - hv, wx));          // alpha_12 of row m after stage 1
-        wyo[(p + 3) & 3] = S(madd(cya, hv - hprev, ym1));  // alpha_11 of row m-1 after stage 1
+        wxo[p & 3] = S(madd(-cxa, hr - hv, wx));
+        wyo[(p + 3) & 3] = S(madd(cya, hv - hprev, ym1));
     };
-
-    // Stage B on iteration it (it >= 5), at node row kB = m - 3.
-    auto stage_b = [&](int it, auto phase) {
+    // B's outputs: alpha_12 of row kB and alpha_11 of the row above.  Heun:
+    // the mean of the state and one more stage; midpoint: the state plus a
+    // full step.
+    auto update_b = [&](auto phase, int it, R hv, R hr, R wx, R ym1, R b12, R b11) {
         constexpr int p = decltype(phase)::value;
         constexpr int h = p & 1, hp = h ^ 1;
         const int bi = it - 5;
-        const R ym1 = R(wyo[p & 3]), y0 = R(wyo[(p + 1) & 3]), yp1 = R(wyo[(p + 2) & 3]);
-        const R wx = R(wxo[(p + 1) & 3]);
-        const R v0 = FIELD ? R(vb_[(p + 1) & 3]) : R(I.v0);
-        const R b12 = R(b12_[(p + 1) & 3]), b11 = R(b11_[p & 3]);   // the step's initial state
-        const R hv = node(ym1, y0, yp1, wx, v0, slB, h, hp, ydmB, ydmsB);
-        const R hr = from_right(hv);
         const R hprev = hhB[hp];
         hhB[h] = hv;
-        {   // Heun: the mean of the state and one more stage; midpoint: the state plus a full step
+        {
             R nv = madd(-cx, hr - hv, MID ? b12 : wx);
             if constexpr (!MID) nv = madd(R(0.5), b12, R(0.5) * nv);
             put(row_ptr<S>(dst12, kB, nx, bi < nrows), off_st, S(nv));
@@ -909,6 +943,36 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
         }
         kBprev = kB;
         kB = next_row(kB, ny);
+    };
+    // A's operands at ring phase p, and the loads of its row m + kFAhead
+    // (none past A's last useful row); the step's initial state of row m
+    // (and of row m-1 for alpha_11) is kept for B.
+    auto operands_a = [&](int it, auto phase, R &ym1, R &y0, R &yp1, R &wx, R &v0) {
+        constexpr int p = decltype(phase)::value;
+        ym1 = R(y[(p + 7) & 7]);
+        y0 = R(y[p]);
+        yp1 = R(y[(p + 1) & 7]);
+        wx = R(wx_[p]);
+        v0 = FIELD ? R(v0_[p]) : R(I.v0);
+        b11_[(p + 3) & 3] = y[(p + 7) & 7];
+        b12_[p & 3] = wx_[p];
+        if constexpr (FIELD) vb_[p & 3] = v0_[p];
+        const bool live = it + kFAhead <= lastA;
+        wx_[(p + kFAhead) & 7] = at(row_ptr<S>(src12, kf, nx, live), off);
+        y[(p + kFAhead + 1) & 7] = at(row_ptr<S>(src11, kf1, nx, live), off);
+        if constexpr (FIELD) v0_[(p + kFAhead) & 7] = at(row_ptr<float>(I.v0f, kf, nx, live), off);
+        kf = kf1;
+        kf1 = next_row(kf1, ny);
+    };
+
+    // Stage A alone on iteration it (ring phase p = it & 7).
+    auto stage_a = [&](int it, auto phase) {
+        constexpr int p = decltype(phase)::value;
+        constexpr int h = p & 1, hp = h ^ 1;
+        R ym1, y0, yp1, wx, v0;
+        operands_a(it, phase, ym1, y0, yp1, wx, v0);
+        const R hv = node(ym1, y0, yp1, wx, v0, slA[hp], slA[h], ydmA, ydmsA);
+        update_a(phase, hv, from_right(hv), wx, ym1);
     };
 
     // A alone on rows k0-2 .. k0+2 (iterations 0 .. 4).
@@ -926,9 +990,30 @@ __device__ __forceinline__ void run_tile_fused(const InstDev &I, int strip, int 
         ydmsB = LK == LK_SUPERBEE ? 2.0f * ydmB : float(theta) * ydmB;
         hhB[0] = R(0);
     }
+    // Iterations from 5 on: A at row m and B at row kB = m - 3, their node
+    // evaluations in lock step (independent: B reads what A wrote on
+    // earlier iterations).
     auto body = [&](int it, auto phase) {
-        stage_a(it, phase);
-        stage_b(it, phase);
+        constexpr int p = decltype(phase)::value;
+        constexpr int h = p & 1, hp = h ^ 1;
+        R ym1a, y0a, yp1a, wxa, v0a;
+        operands_a(it, phase, ym1a, y0a, yp1a, wxa, v0a);
+        const R ym1b = R(wyo[p & 3]), y0b = R(wyo[(p + 1) & 3]), yp1b = R(wyo[(p + 2) & 3]);
+        const R wxb = R(wxo[(p + 1) & 3]);
+        const R v0b = FIELD ? R(vb_[(p + 1) & 3]) : R(I.v0);
+        const R b12 = R(b12_[(p + 1) & 3]), b11 = R(b11_[p & 3]);   // the step's initial state
+        F2 s0, ydm(ydmA, ydmB), ydms(ydmsA, ydmsB);
+        const F2 hv = node(F2(ym1a, ym1b), F2(y0a, y0b), F2(yp1a, yp1b), F2(wxa, wxb), F2(v0a, v0b),
+                           F2(slA[hp], slB[hp]), s0, ydm, ydms);
+        slA[h] = s0.a;
+        slB[h] = s0.b;
+        ydmA = ydm.a;
+        ydmsA = ydms.a;
+        ydmB = ydm.b;
+        ydmsB = ydms.b;
+        const F2 hr = from_right(hv);
+        update_a(phase, hv.a, hr.a, wxa, ym1a);
+        update_b(phase, it, hv.b, hr.b, wxb, ym1b, b12, b11);
     };
     for (int it = 5;; it += 8) {
         body(it, Phase<5>{});
