@@ -258,12 +258,12 @@ def fp64_state_leg(fdm, K, warm, repeats, inputs, log):
                "timing": "HIP events around K back-to-back steps, median of %d" % repeats}
 
 
-def loop_leg(fdm, W_, K, warm, repeats, autotune, log):
+def loop_leg(fdm, W_, K, warm, repeats, autotune, log, schedule="auto", tile_rows=0):
     import torch
     a11, a12 = W_.ring(2048, 2048, R=300.0, sigma=6.0)
     stream = torch.cuda.current_stream()
     r = single_instance(fdm, a11, a12, K, warm, repeats, stream, dict(limiter="superbee", cfl=0.4, v0=-1.0),
-                        {"schedule": "auto"}, autotune)
+                        {"schedule": schedule, "tile_rows": tile_rows}, autotune)
     value = r["cells"] * K / r["seconds"]
     log("bench[c2]: %.4e cell-updates/s (%s, %d rows)" % (value, r["schedule"], r["tile_rows"]))
     return r, {"grid": [2048, 2048], "limiter": "superbee", "cfl": 0.4, "steps": K,
@@ -607,6 +607,9 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="skip every leg but the headline")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
+    ap.add_argument("--loop-schedule", default="auto", choices=["auto", "plain", "fused"],
+                    help="schedule of the 2048^2 loop leg (with --no-autotune: the one timed)")
+    ap.add_argument("--loop-rows", type=int, default=0, help="tile rows of the loop leg (0: the default rule)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--batched-schedules", default="batched,plain,fused",
@@ -651,7 +654,8 @@ def main():
     if not args.no_fp64:
         fp64, extra["fp64_state"] = fp64_state_leg(fdm, K, warm, args.repeats, inputs, log)
     if not args.no_loop:
-        r2, extra["loop_2048"], ins = loop_leg(fdm, W_, K, warm, args.repeats, autotune, log)
+        r2, extra["loop_2048"], ins = loop_leg(fdm, W_, K, warm, args.repeats, autotune, log,
+                                               args.loop_schedule, args.loop_rows)
         loop = (r2, ins)
     if not args.no_fd:
         r3, extra["fully_discrete"], ins = fully_discrete_leg(fdm, W_, K, warm, args.repeats, autotune, log)
