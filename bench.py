@@ -82,10 +82,12 @@ def _counter_rows(directories, counters):
 
 
 def write_profile_summary(fetch_dir, write_dir, sq_dir, out, copy_n, tile_rows):
-    """Per-launch counters of the headline kernel from three rocprofv3 passes
-    (FETCH_SIZE, WRITE_SIZE, SQ): HBM-side bytes, each counter calibrated by
-    what it reads for a copy kernel of 4 copy_n^2 bytes each way, and the
-    VALU and MFMA instructions issued."""
+    """Per-launch counters of the headline kernel at one tile height from
+    three rocprofv3 passes (FETCH_SIZE, WRITE_SIZE, SQ): HBM-side bytes, each
+    counter calibrated by what it reads for a copy kernel of 4 copy_n^2 bytes
+    each way, and the VALU and MFMA instructions issued.  Stored in `out`
+    under by_rows[tile_rows], beside the entries of other heights taken on
+    the same kernel sources (a summary of other sources is replaced)."""
     def pick(vals, pat, counter):
         for name, cs in vals.items():
             if pat in name and counter in cs:
@@ -102,28 +104,50 @@ def write_profile_summary(fetch_dir, write_dir, sq_dir, out, copy_n, tile_rows):
     sq = {c: pick(sv, HEADLINE_KERNEL, c) for c in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_MFMA",
                                                      "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY")
           if any(HEADLINE_KERNEL in n and c in cs for n, cs in sv.items())}
+    entry = {"copy_probe_n": copy_n, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
+             "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+             "bytes_per_launch": round((fk * ff + wk * wf) * 1024.0),
+             "sq_per_launch": {k: round(v, 1) for k, v in sq.items()}}
     summary = {"kernel": HEADLINE_KERNEL, "kernel_source_sha256": kernel_source_hash(), "grid": 4096,
-               "tile_rows": tile_rows, "copy_probe_n": copy_n,
-               "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
-               "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
-               "bytes_per_launch": round((fk * ff + wk * wf) * 1024.0),
-               "sq_per_launch": {k: round(v, 1) for k, v in sq.items()}}
+               "by_rows": {}}
+    try:
+        with open(out) as fh:
+            old = json.load(fh)
+        if old.get("kernel_source_sha256") == summary["kernel_source_sha256"] and isinstance(old.get("by_rows"),
+                                                                                              dict):
+            summary["by_rows"] = old["by_rows"]
+    except (OSError, ValueError):
+        pass
+    summary["by_rows"][str(int(tile_rows))] = entry
+    summary["by_rows"] = {k: summary["by_rows"][k] for k in sorted(summary["by_rows"], key=int)}
     with open(out, "w") as fh:
         json.dump(summary, fh, indent=1)
     print(json.dumps(summary))
 
 
-def load_profile(tile_rows):
-    """The headline kernel's counter summary when it was measured on the
-    current kernel sources at this tile height, else None."""
+def _profile_entries():
+    """{tile rows: counter entry} of the committed summary when it was taken
+    on the current kernel sources, else {}."""
     try:
         with open(PROFILE_FILE) as fh:
             p = json.load(fh)
     except (OSError, ValueError):
-        return None
-    if p.get("kernel_source_sha256") != kernel_source_hash() or p.get("tile_rows") != tile_rows:
-        return None
-    return p
+        return {}
+    if p.get("kernel_source_sha256") != kernel_source_hash() or not isinstance(p.get("by_rows"), dict):
+        return {}
+    return {int(k): v for k, v in p["by_rows"].items()}
+
+
+def profiled_heights():
+    """Tile heights the committed counter summary covers (current sources)."""
+    return sorted(_profile_entries())
+
+
+def load_profile(tile_rows):
+    """The headline kernel's counters at this tile height, measured on the
+    current kernel sources, else None."""
+    e = _profile_entries().get(int(tile_rows))
+    return dict(e, tile_rows=int(tile_rows)) if e else None
 
 
 # ------------------------------------------------------------------ helpers
@@ -150,12 +174,12 @@ def timed_steps(fdm, ctx, t11, t12, K, repeats, stream):
 
 
 def single_instance(fdm, a11, a12, K, W, repeats, stream, desc_kw, options, autotune, field=None,
-                    prefer_rows=None):
+                    prefer_rows=()):
     """Autotune, a K-step run from the inputs (kept for parity), W warmup
     steps, then the timed K-step repeats.  Returns timing and the state
-    after the first K steps.  prefer_rows: a fused tile height to keep when
-    the autotuner timed it within 3% of its best (the height the counter
-    passes were taken at)."""
+    after the first K steps.  prefer_rows: fused tile heights the counter
+    passes were taken at; when the autotuner's best is none of them, the
+    fastest of them it timed within 3% of its best is kept instead."""
     import numpy as np
     import torch
     dev = torch.device("cuda:0")
@@ -172,12 +196,13 @@ def single_instance(fdm, a11, a12, K, W, repeats, stream, desc_kw, options, auto
         trials = fdm.fdm_autotune(ctx, [t11], [t12], trial_steps=20)
         best = min(trials, key=lambda t: t["seconds_per_step"])
         sched, choice = best["schedule"], "autotuned"
-        near = [t for t in trials if t["schedule"] == "fused" and t["tile_rows"] == prefer_rows and
+        near = [t for t in trials if t["schedule"] == "fused" and t["tile_rows"] in prefer_rows and
                 t["seconds_per_step"] <= PROFILED_HEIGHT_SLACK * best["seconds_per_step"]]
-        if near and (best["schedule"], best["tile_rows"]) != ("fused", prefer_rows):
+        if near and not (best["schedule"] == "fused" and best["tile_rows"] in prefer_rows):
+            rows = min(near, key=lambda t: t["seconds_per_step"])["tile_rows"]
             fdm.fdm_destroy(ctx)
             ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, v0_field=field, **desc_kw),
-                                         options=dict(options, schedule="fused", tile_rows=prefer_rows),
+                                         options=dict(options, schedule="fused", tile_rows=rows),
                                          stream=stream, keep=[field] if field is not None else [])
             sched, choice = "fused", "profiled height, within 3% of the autotuned best"
     rows = fdm.fdm_tile_rows(ctx, 0)
@@ -200,12 +225,7 @@ def headline_leg(fdm, W_, K, warm, repeats, autotune, tile_rows, schedule, log):
     a11, a12, v0 = W_.bands_and_celerity(4096, seed=3)
     stream = torch.cuda.current_stream()
     tv = torch.from_numpy(v0).to("cuda:0")
-    try:
-        with open(PROFILE_FILE) as fh:
-            p = json.load(fh)
-        prefer = p["tile_rows"] if p.get("kernel_source_sha256") == kernel_source_hash() else None
-    except (OSError, ValueError, KeyError):
-        prefer = None
+    prefer = profiled_heights()
     r = single_instance(fdm, a11, a12, K, warm, repeats, stream, dict(limiter="minmod", cfl=0.45),
                         {"schedule": schedule, "tile_rows": tile_rows}, autotune, field=tv, prefer_rows=prefer)
     cells = r["cells"]

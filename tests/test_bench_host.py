@@ -37,17 +37,28 @@ def test_profile_summary_calibrates_by_the_copy_kernel(tmp_path, monkeypatch):
     out = tmp_path / "p.json"
     bench.write_profile_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s"), str(out), n, 43)
     p = json.loads(out.read_text())
-    assert p["fetch_factor"] == 2.0 and p["write_factor"] == 1.0
-    assert p["bytes_per_launch"] == round((1100 * 2.0 + 3000 * 1.0) * 1024)
-    assert p["sq_per_launch"] == {"SQ_INSTS_VALU": 200.0, "SQ_INSTS_MFMA": 0.0, "SQ_WAVES": 50.0}
-    assert p["tile_rows"] == 43 and p["kernel_source_sha256"] == bench.kernel_source_hash()
-    # looked up only at the profiled height, and only while the kernels are unchanged
+    e = p["by_rows"]["43"]
+    assert e["fetch_factor"] == 2.0 and e["write_factor"] == 1.0
+    assert e["bytes_per_launch"] == round((1100 * 2.0 + 3000 * 1.0) * 1024)
+    assert e["sq_per_launch"] == {"SQ_INSTS_VALU": 200.0, "SQ_INSTS_MFMA": 0.0, "SQ_WAVES": 50.0}
+    assert p["kernel_source_sha256"] == bench.kernel_source_hash()
+    # a second height joins the first (same sources)
+    _csv(str(tmp_path / "f"), [(k, 1, "FETCH_SIZE", 900), (c, 1, "FETCH_SIZE", 2048)])
+    bench.write_profile_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s"), str(out), n, 60)
+    p = json.loads(out.read_text())
+    assert list(p["by_rows"]) == ["43", "60"]
+    assert p["by_rows"]["60"]["bytes_per_launch"] == round((900 * 2.0 + 3000 * 1.0) * 1024)
+    # looked up only at a profiled height, and only while the kernels are unchanged
     monkeypatch.setattr(bench, "PROFILE_FILE", str(out))
-    assert bench.load_profile(43)["bytes_per_launch"] == p["bytes_per_launch"]
+    assert bench.profiled_heights() == [43, 60]
+    assert bench.load_profile(43)["bytes_per_launch"] == round((1100 * 2.0 + 3000 * 1.0) * 1024)
     assert bench.load_profile(42) is None
     p["kernel_source_sha256"] = "0" * 64
     out.write_text(json.dumps(p))
-    assert bench.load_profile(43) is None
+    assert bench.load_profile(43) is None and bench.profiled_heights() == []
+    # a summary of other sources is replaced, not merged
+    bench.write_profile_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s"), str(out), n, 50)
+    assert list(json.loads(out.read_text())["by_rows"]) == ["50"]
 
 
 def test_parity_record_hand_values():
@@ -88,9 +99,11 @@ def test_committed_counter_summary_is_well_formed():
         pytest.skip("no counter summary committed yet")
     with open(bench.PROFILE_FILE) as fh:
         t = json.load(fh)
-    assert len(t["kernel_source_sha256"]) == 64 and t["grid"] == 4096 and t["bytes_per_launch"] > 0
-    assert 1.9 < t["fetch_factor"] < 2.1 and 0.9 < t["write_factor"] < 1.1
-    assert t["sq_per_launch"]["SQ_INSTS_VALU"] > 0 and t["sq_per_launch"].get("SQ_INSTS_MFMA", 0) == 0
+    assert len(t["kernel_source_sha256"]) == 64 and t["grid"] == 4096 and t["by_rows"]
+    for rows, e in t["by_rows"].items():
+        assert int(rows) > 0 and e["bytes_per_launch"] > 0
+        assert 1.9 < e["fetch_factor"] < 2.1 and 0.9 < e["write_factor"] < 1.1
+        assert e["sq_per_launch"]["SQ_INSTS_VALU"] > 0 and e["sq_per_launch"].get("SQ_INSTS_MFMA", 0) == 0
 
 
 def test_more_than_one_gpu_is_refused():
