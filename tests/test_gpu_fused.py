@@ -219,6 +219,37 @@ def test_fused_graph_chunks_bitwise(fdm, chunk):
     assert outs[0][2] == outs[1][2]
 
 
+@pytest.mark.parametrize("schedule", ["fused", "plain"])
+def test_graph_replays_each_equal_direct_steps(fdm, schedule):
+    """fdm_run keeps one captured graph per chunk length and array set: call
+    it four times for one chunk each (one capture, three replays), with
+    eager device work, a host copy and a synchronisation between calls, and
+    compare every replay bitwise with the same steps enqueued directly."""
+    import torch
+    a11, a12 = W.ring(150, 110, R=28.0, sigma=3.0)
+    opts = {"schedule": schedule}
+    ctxs, states = [], []
+    for _ in range(2):
+        ctxs.append(fdm.fdm_transport_init(fdm.desc(150, 110, limiter="superbee", cfl=0.4, v0=-1.0),
+                                           options=opts))
+        states.append((to_dev(a11), to_dev(a12)))
+    (g11, g12), (e11, e12) = states
+    chunk = 6
+    for rep in range(4):
+        assert fdm.fdm_run(ctxs[0], g11, g12, chunk, chunk, history=False) is None
+        fdm.fdm_transport_step(ctxs[1], e11, e12, chunk)
+        torch.cuda.synchronize()
+        assert np.array_equal(g11.cpu().numpy(), e11.cpu().numpy()), rep
+        assert np.array_equal(g12.cpu().numpy(), e12.cpu().numpy()), rep
+        assert fdm.fdm_transport_stats(ctxs[0], g11, g12) == fdm.fdm_transport_stats(ctxs[1], e11, e12)
+        # eager work of the caller's own on the device between replays
+        scratch = (g11 * 2.0 + e12).sum()
+        torch.cuda.synchronize()
+        assert np.isfinite(float(scratch))
+    for c in ctxs:
+        fdm.fdm_destroy(c)
+
+
 def test_fused_several_instances_equal_batched(fdm):
     """Several instances: one batched fused launch per step for all of them
     (different sizes, limiters, a celerity field, a prescribed velocity)."""
