@@ -145,6 +145,10 @@ double static_mean_stress(const fdm_static_desc &d, const fdm::StaticParams &q)
     return 2.0 * d.mu * d.eps13 - d.mu * d.phi_mean * (double)q.h / (double)q.n3;
 }
 
+// Tiles (one wave64 each) of one launch: a dispatch holds fewer than 2^32
+// work-items, and the grid rounds the tile count up by at most 31.
+constexpr int64_t kMaxLaunchTiles = (int64_t)1 << 25;
+
 // Tallest balanced height the autotuner tries (one round of waves over a
 // 8192^2 grid needs 149 rows).
 constexpr int kMaxBalancedRows = 512;
@@ -158,7 +162,7 @@ int64_t launch_waves(const fdm_ctx *c, bool fused, bool batched, int rows)
     for (const fdm_transport_desc &d : c->desc) {
         const int r = std::min(rows, d.ny);
         const int w = fused ? fdm::kFusedStrip : fdm::kStrip;
-        const int64_t t = (int64_t)((d.nx + w - 1) / w) * ((d.ny + r - 1) / r);
+        const int64_t t = (int64_t)((d.nx + w - 1) / w) * fdm::tiles_along_y(d.ny, r);
         total += t;
         largest = std::max(largest, t);
     }
@@ -298,7 +302,13 @@ fdm_status retile(fdm_ctx *c, int requested)
         I.rows = pick_rows(c->batched ? batch_strip_rows : strip_rows_of(d), d.ny, requested);
         I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
         I.fstrips = (d.nx + fdm::kFusedStrip - 1) / fdm::kFusedStrip;
-        I.chunks = (d.ny + I.rows - 1) / I.rows;
+        // a launch of one instance must fit one dispatch: taller tiles where
+        // the height asked for would exceed it (one- and two-column grids
+        // of more than 2^30 rows)
+        const int64_t strips = c->fused ? I.fstrips : I.strips;
+        while (strips * fdm::tiles_along_y(d.ny, I.rows) > kMaxLaunchTiles && I.rows < d.ny)
+            I.rows = (int)std::min<int64_t>(d.ny, 2 * (int64_t)I.rows);
+        I.chunks = fdm::tiles_along_y(d.ny, I.rows);
         I.tile_begin = tile;   // in the tiling of the schedule's kernel
         tile += (int64_t)(c->fused ? I.fstrips : I.strips) * I.chunks;
     }
@@ -309,7 +319,7 @@ fdm_status retile(fdm_ctx *c, int requested)
         c->graph = nullptr;
     }
     if (!c->batched) return FDM_OK;
-    if (tile >= ((int64_t)1 << 31)) return fail(c, FDM_ERR_INVALID_ARG, "too many tiles for one batched launch");
+    if (tile > kMaxLaunchTiles) return fail(c, FDM_ERR_INVALID_ARG, "too many tiles for one batched launch");
     // the map and table buffers may still feed queued work
     FDM_HIP(c, hipStreamSynchronize(c->stream));
     if (tile > c->tile_capacity) {
@@ -440,7 +450,7 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
         // the stage kernels' default tiling, as on a plain context: the per-tile
         // sums then add in the same order whatever the schedule
         I.rows = pick_rows(strip_rows_of(d), d.ny, 0);
-        I.chunks = (d.ny + I.rows - 1) / I.rows;
+        I.chunks = fdm::tiles_along_y(d.ny, I.rows);
     }
     const int64_t tiles = (int64_t)I.strips * I.chunks;
     if (tiles > w.cap) {

@@ -15,6 +15,13 @@ constexpr int kHalo = 2;
 constexpr int kStrip = kWave - 2 * kHalo;   // 60 output columns per wave
 constexpr int kFusedStrip = kWave - 8;      // 56: the fused Heun kernel's (4 halo lanes a side)
 constexpr int kWavesPerBlock = 4;
+
+// Row tiles of a grid of ny rows (ny may be as large as 2^31 - 1, so the
+// rounding-up sum is taken in 64 bits).
+__host__ __device__ inline int tiles_along_y(int ny, int rows)
+{
+    return (int)(((int64_t)ny + rows - 1) / rows);
+}
 constexpr int kBlock = kWave * kWavesPerBlock;
 
 // Limiter and Hamiltonian codes (values of the public enums).

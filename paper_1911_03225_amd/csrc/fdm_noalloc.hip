@@ -126,7 +126,7 @@ extern "C" fdm_status fdm_transport_step_noalloc(const fdm_transport_desc *desc,
     I.rows = pick_rows(strip_rows_of(d), d.ny, 0);
     I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
     I.fstrips = (d.nx + fdm::kFusedStrip - 1) / fdm::kFusedStrip;
-    I.chunks = (d.ny + I.rows - 1) / I.rows;
+    I.chunks = fdm::tiles_along_y(d.ny, I.rows);
     for (int32_t step = 0; step < n_steps; ++step) {
         int modes[2];
         const int nm = stage_modes(order, step, modes);

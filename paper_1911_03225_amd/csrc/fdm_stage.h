@@ -1160,7 +1160,7 @@ template <int LK, int VK, bool FIELD, bool MID>
 hipError_t launch_fused_t(const InstDev &I, int dir, hipStream_t s)
 {
     const int strips = (I.nx + kFStrip - 1) / kFStrip;
-    const int64_t tiles = (int64_t)strips * ((I.ny + I.rows - 1) / I.rows);
+    const int64_t tiles = (int64_t)strips * tiles_along_y(I.ny, I.rows);
     const int64_t blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per_xcd = (int)((blocks + 7) / 8);
     hipLaunchKernelGGL((fused_kernel<LK, VK, FIELD, MID>), dim3(8 * per_xcd), dim3(kBlock), 0, s, I, tiles, per_xcd,

@@ -1,0 +1,142 @@
+"""Grids at the descriptor's size limits (nx*ny < 2^31 nodes, nx < 2^27).
+
+Seeded ring patches (the loop workload's cross-section) sit in a field of
+zeros, at the far end of the arrays and across the periodic seams.  Zero
+regions stay exactly zero under the scheme (H(0) = 0 and the update of a
+node whose stencil holds only zeros is zero), and over a few steps a
+patch's support grows by a few nodes per stage, so each window around a
+patch evolves as the same window would on a periodic grid of its own: the
+oracle runs that small grid and the comparison is node by node.  The rest
+of the big arrays must still be exactly zero, and the FP64 statistics over
+the whole grid must equal the sums over the windows.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from gpu_util import oracle_problem, rel_l1, rel_linf, tolerance
+from paper_1911_03225_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 3
+PAD = 32   # zeros around a patch: more than the support grows in STEPS Heun steps
+
+
+@pytest.fixture(scope="module")
+def fdm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_03225_amd import fdm as F
+    F.load_library()
+    return F
+
+
+def _window_index(torch, start, length, n):
+    return torch.arange(start, start + length, dtype=torch.int64, device="cuda:0") % n
+
+
+def _run_case(fdm, oracle, ny, nx, patch_shape, sites, options, exact=False, **kw):
+    import torch
+    dtype = torch.float64 if options.get("precision") == "fp64" else torch.float32
+    ph, pw = patch_shape
+    wh = ny if ph == ny else ph + 2 * PAD
+    ww = nx if pw == nx else pw + 2 * PAD
+    R = min(ph, pw) / 4.0 if min(ph, pw) > 1 else ph / 4.0
+    a11p, a12p = W.ring(pw, ph, R=R, sigma=max(1.0, R / 6.0))
+    wins = []
+    for r0, c0 in sites:
+        w11 = np.zeros((wh, ww))
+        w12 = np.zeros((wh, ww))
+        oy, ox = (0 if wh == ph else PAD), (0 if ww == pw else PAD)
+        # the float32-rounded values: both sides start from the same numbers
+        w11[oy:oy + ph, ox:ox + pw] = a11p.astype(np.float32)
+        w12[oy:oy + ph, ox:ox + pw] = a12p.astype(np.float32)
+        wins.append((r0, c0, w11, w12))
+
+    print("max-size case", ny, nx, options, flush=True)
+    t11 = torch.zeros((ny, nx), dtype=dtype, device="cuda:0")
+    t12 = torch.zeros((ny, nx), dtype=dtype, device="cuda:0")
+    idx = []
+    for r0, c0, w11, w12 in wins:
+        rows, cols = _window_index(torch, r0, wh, ny), _window_index(torch, c0, ww, nx)
+        t11[rows[:, None], cols[None, :]] = torch.from_numpy(w11).to("cuda:0", dtype)
+        t12[rows[:, None], cols[None, :]] = torch.from_numpy(w12).to("cuda:0", dtype)
+        idx.append((rows, cols))
+    ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, **kw), options=options)
+    try:
+        rows_used = fdm.fdm_tile_rows(ctx, 0)
+        dt = fdm.fdm_transport_dt(ctx)
+        fdm.fdm_transport_step(ctx, t11, t12, STEPS)
+        torch.cuda.synchronize()
+        st = fdm.fdm_transport_stats(ctx, t11, t12)[0]
+    finally:
+        fdm.fdm_destroy(ctx)
+
+    P = oracle_problem(oracle, ww, wh, dt, **kw)
+    sum_abs, max_norm = 0.0, 0.0
+    for (r0, c0, w11, w12), (rows, cols) in zip(wins, idx):
+        g11 = t11[rows[:, None], cols[None, :]].double().cpu().numpy()
+        g12 = t12[rows[:, None], cols[None, :]].double().cpu().numpy()
+        o11, o12 = oracle.run(P, w11, w12, STEPS)
+        e1 = rel_l1(g11, g12, o11, o12, w11, w12)
+        einf = rel_linf(g11, g12, o11, o12, w11, w12)
+        if exact:
+            assert np.array_equal(g11, o11) and np.array_equal(g12, o12), (r0, c0, e1, einf)
+        else:
+            assert e1 <= tolerance(STEPS) and einf <= 1e-4, (r0, c0, e1, einf)
+        sum_abs += np.abs(g11).sum() + np.abs(g12).sum()
+        max_norm = max(max_norm, float(np.sqrt(g11 * g11 + g12 * g12).max()))
+        t11[rows[:, None], cols[None, :]] = 0
+        t12[rows[:, None], cols[None, :]] = 0
+    assert st["sum_abs"] == pytest.approx(sum_abs, rel=1e-12)
+    assert st["max_norm"] == pytest.approx(max_norm, rel=1e-15)
+    assert int(torch.count_nonzero(t11)) == 0 and int(torch.count_nonzero(t12)) == 0
+    del t11, t12
+    torch.cuda.empty_cache()
+    return rows_used
+
+
+SQUARE = 46340   # 46340^2 = 2^31 - 87952 nodes
+
+
+@pytest.mark.parametrize("schedule", ["fused", "plain"])
+def test_largest_square_grid(fdm, oracle, schedule):
+    """46340^2 nodes (8.6 GB per float32 array): a patch across the corner
+    seam (both axes wrap), one ending on the last row, one inside."""
+    n = SQUARE
+    sites = [(n - 64, n - 64), (n - 128, n // 2), (n // 2 + 7, 1000)]
+    _run_case(fdm, oracle, n, n, (64, 64), sites, {"schedule": schedule},
+              limiter="superbee", cfl=0.4, v0=-1.0)
+
+
+def test_largest_square_grid_fp64_state_bitwise(fdm, oracle):
+    """The same grid with float64 state (17 GB per array): bit for bit the
+    oracle's values in every window."""
+    n = SQUARE
+    sites = [(n - 64, n - 64), (n // 2 + 7, 1000)]
+    _run_case(fdm, oracle, n, n, (64, 64), sites, {"precision": "fp64"}, exact=True,
+              limiter="mc", cfl=0.4, v0=-1.0)
+
+
+def test_widest_rows(fdm, oracle):
+    """nx = 2^27 - 1 (a row of 512 MiB) and 15 rows, periodic in y through
+    the whole window: patches across the x seam and in the last strip."""
+    nx, ny = (1 << 27) - 1, 15
+    sites = [(0, nx - 64), (0, nx - 300), (0, nx // 3)]
+    _run_case(fdm, oracle, ny, nx, (15, 64), sites, {"schedule": "fused"},
+              limiter="minmod", cfl=0.4, v0=-1.0)
+
+
+@pytest.mark.parametrize("schedule", ["fused", "plain"])
+def test_tallest_column(fdm, oracle, schedule):
+    """nx = 1 and ny = 2^31 - 1: the tile height is raised until the launch
+    fits one dispatch (2^25 tiles), the tile count is rounded up without
+    overflowing, and the y walk crosses row 2^31 - 2 into row 0."""
+    nx, ny = 1, (1 << 31) - 1
+    sites = [(ny - 64, 0), (ny // 2, 0)]
+    rows = _run_case(fdm, oracle, ny, nx, (64, 1), sites, {"schedule": schedule},
+                     limiter="superbee", cfl=0.4, v0=-1.0)
+    assert rows == 64
