@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import struct
 import sys
 import time
 
@@ -41,8 +42,9 @@ STATE_BYTES = {"fp32": 16, "fp64": 32}
 FIELD_BYTES = 4
 
 PROFILE_FILE = os.path.join(ROOT, "profiles", "fused_kernel_bands_field_4096_fp32_counters.json")
-KERNEL_SOURCES = ["fdm_stage.h", "fdm_stage_f32.hip", "fdm_internal.h", "fdm_kernels.hip"]
+LIB_FILE = os.path.join(ROOT, "paper_1911_03225_amd", "libfdm.so")
 HEADLINE_KERNEL = "fused_kernel<3, 0, true, false>"   # minmod, LAW, celerity field, Heun
+HEADLINE_SYMBOL = "_ZN3fdm12_GLOBAL__N_112fused_kernelILi3ELi0ELb1ELb0EEEvNS_7InstDevEliii"
 # Repeated autotuner runs on one box order heights within about 3% of each
 # other differently; within that the height the counters were taken at is kept.
 PROFILED_HEIGHT_SLACK = 1.03
@@ -54,12 +56,69 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1911_03225_amd", "csrc", f), "rb") as fh:
-            h.update(f.encode() + b"\0" + fh.read())
-    return h.hexdigest()
+def _elf_sections(b):
+    """[name, type, addr, offset, size, link] of each section of an ELF64 image."""
+    shoff, = struct.unpack_from("<Q", b, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
+    secs = []
+    for i in range(shnum):
+        o = shoff + i * shentsize
+        name, typ = struct.unpack_from("<II", b, o)
+        addr, off, size = struct.unpack_from("<QQQ", b, o + 16)
+        link, = struct.unpack_from("<I", b, o + 40)
+        secs.append([name, typ, addr, off, size, link])
+    names = secs[shstrndx][3]
+    for s in secs:
+        s[0] = b[names + s[0]:b.index(b"\0", names + s[0])].decode()
+    return secs
+
+
+def kernel_code_hash(path=LIB_FILE, symbol=HEADLINE_SYMBOL, arch="gfx950"):
+    """SHA-256 of a kernel as built: its machine code and its kernel
+    descriptor (registers, LDS, launch settings; without the entry offset,
+    which moves with the rest of the code object), read from the library's
+    offload bundles.  None when the library or the kernel is not there.  The
+    counter summary is keyed by it, so the counters stay valid across edits
+    that leave the headline kernel's code unchanged, and only those."""
+    try:
+        with open(path, "rb") as fh:
+            b = fh.read()
+        fat = [s for s in _elf_sections(b) if s[0] == ".hip_fatbin"]
+        if not fat:
+            return None
+        data = b[fat[0][3]:fat[0][3] + fat[0][4]]
+        magic = b"__CLANG_OFFLOAD_BUNDLE__"
+        base = data.find(magic)
+        while base >= 0:
+            n, = struct.unpack_from("<Q", data, base + len(magic))
+            p = base + len(magic) + 8
+            for _ in range(n):
+                off, size, tl = struct.unpack_from("<QQQ", data, p)
+                triple = data[p + 24:p + 24 + tl].decode()
+                p += 24 + tl
+                if not triple.endswith("--" + arch):
+                    continue
+                elf = data[base + off:base + off + size]
+                secs = _elf_sections(elf)
+                found = {}
+                for st in (s for s in secs if s[1] == 2):          # SHT_SYMTAB
+                    strtab = secs[st[5]][3]
+                    for k in range(st[4] // 24):
+                        o = st[3] + 24 * k
+                        nm, _info, _other, shndx = struct.unpack_from("<IBBH", elf, o)
+                        val, sz = struct.unpack_from("<QQ", elf, o + 8)
+                        name = elf[strtab + nm:elf.index(b"\0", strtab + nm)].decode()
+                        if name in (symbol, symbol + ".kd") and shndx < len(secs):
+                            sec = secs[shndx]
+                            start = sec[3] + val - sec[2]
+                            found[name] = elf[start:start + sz]
+                if symbol in found and len(found.get(symbol + ".kd", b"")) == 64:
+                    kd = found[symbol + ".kd"]
+                    return hashlib.sha256(found[symbol] + kd[:16] + kd[24:]).hexdigest()
+            base = data.find(magic, base + 1)
+    except (OSError, ValueError, struct.error, IndexError, UnicodeDecodeError):
+        return None
+    return None
 
 
 # ------------------------------------------------------------ counter summary
@@ -108,13 +167,13 @@ def write_profile_summary(fetch_dir, write_dir, sq_dir, out, copy_n, tile_rows):
              "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
              "bytes_per_launch": round((fk * ff + wk * wf) * 1024.0),
              "sq_per_launch": {k: round(v, 1) for k, v in sq.items()}}
-    summary = {"kernel": HEADLINE_KERNEL, "kernel_source_sha256": kernel_source_hash(), "grid": 4096,
+    summary = {"kernel": HEADLINE_KERNEL, "kernel_code_sha256": kernel_code_hash(), "grid": 4096,
                "by_rows": {}}
     try:
         with open(out) as fh:
             old = json.load(fh)
-        if old.get("kernel_source_sha256") == summary["kernel_source_sha256"] and isinstance(old.get("by_rows"),
-                                                                                              dict):
+        if summary["kernel_code_sha256"] and old.get("kernel_code_sha256") == summary["kernel_code_sha256"] and \
+                isinstance(old.get("by_rows"), dict):
             summary["by_rows"] = old["by_rows"]
     except (OSError, ValueError):
         pass
@@ -127,25 +186,26 @@ def write_profile_summary(fetch_dir, write_dir, sq_dir, out, copy_n, tile_rows):
 
 def _profile_entries():
     """{tile rows: counter entry} of the committed summary when it was taken
-    on the current kernel sources, else {}."""
+    on the headline kernel's current machine code, else {}."""
     try:
         with open(PROFILE_FILE) as fh:
             p = json.load(fh)
     except (OSError, ValueError):
         return {}
-    if p.get("kernel_source_sha256") != kernel_source_hash() or not isinstance(p.get("by_rows"), dict):
+    code = kernel_code_hash()
+    if not code or p.get("kernel_code_sha256") != code or not isinstance(p.get("by_rows"), dict):
         return {}
     return {int(k): v for k, v in p["by_rows"].items()}
 
 
 def profiled_heights():
-    """Tile heights the committed counter summary covers (current sources)."""
+    """Tile heights the committed counter summary covers (current kernel code)."""
     return sorted(_profile_entries())
 
 
 def load_profile(tile_rows):
-    """The headline kernel's counters at this tile height, measured on the
-    current kernel sources, else None."""
+    """The headline kernel's counters at this tile height, measured on its
+    current machine code, else None."""
     e = _profile_entries().get(int(tile_rows))
     return dict(e, tile_rows=int(tile_rows)) if e else None
 

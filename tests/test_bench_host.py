@@ -27,6 +27,7 @@ def _csv(path, rows):
 def test_profile_summary_calibrates_by_the_copy_kernel(tmp_path, monkeypatch):
     """FETCH_SIZE and WRITE_SIZE are scaled by what they read for a copy of
     known size; SQ counters are averaged per launch."""
+    monkeypatch.setattr(bench, "kernel_code_hash", lambda *a, **k: "c" * 64)
     k = "void fdm::(anonymous namespace)::" + bench.HEADLINE_KERNEL + "(fdm::InstDev, long, int, int, int)"
     c = "void fdm::(anonymous namespace)::" + bench.COPY_KERNEL + "(float*, float const*, long)"
     n = 1024                                   # copy of 4 MiB each way = 4096 KiB
@@ -41,7 +42,7 @@ def test_profile_summary_calibrates_by_the_copy_kernel(tmp_path, monkeypatch):
     assert e["fetch_factor"] == 2.0 and e["write_factor"] == 1.0
     assert e["bytes_per_launch"] == round((1100 * 2.0 + 3000 * 1.0) * 1024)
     assert e["sq_per_launch"] == {"SQ_INSTS_VALU": 200.0, "SQ_INSTS_MFMA": 0.0, "SQ_WAVES": 50.0}
-    assert p["kernel_source_sha256"] == bench.kernel_source_hash()
+    assert p["kernel_code_sha256"] == "c" * 64
     # a second height joins the first (same sources)
     _csv(str(tmp_path / "f"), [(k, 1, "FETCH_SIZE", 900), (c, 1, "FETCH_SIZE", 2048)])
     bench.write_profile_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s"), str(out), n, 60)
@@ -53,12 +54,26 @@ def test_profile_summary_calibrates_by_the_copy_kernel(tmp_path, monkeypatch):
     assert bench.profiled_heights() == [43, 60]
     assert bench.load_profile(43)["bytes_per_launch"] == round((1100 * 2.0 + 3000 * 1.0) * 1024)
     assert bench.load_profile(42) is None
-    p["kernel_source_sha256"] = "0" * 64
+    p["kernel_code_sha256"] = "0" * 64
     out.write_text(json.dumps(p))
     assert bench.load_profile(43) is None and bench.profiled_heights() == []
-    # a summary of other sources is replaced, not merged
+    # a summary of other kernel code is replaced, not merged
     bench.write_profile_summary(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "s"), str(out), n, 50)
     assert list(json.loads(out.read_text())["by_rows"]) == ["50"]
+
+
+def test_kernel_code_hash_reads_the_built_kernel():
+    """The hash covers one kernel's machine code and descriptor in the
+    library's gfx950 code object: stable, different per kernel, None for a
+    missing kernel or library."""
+    if not os.path.exists(bench.LIB_FILE):
+        pytest.skip("libfdm.so not built")
+    h = bench.kernel_code_hash()
+    assert h is not None and len(h) == 64 and h == bench.kernel_code_hash()
+    other = bench.HEADLINE_SYMBOL.replace("ILi3ELi0ELb1ELb0E", "ILi2ELi0ELb0ELb0E")
+    assert bench.kernel_code_hash(symbol=other) not in (None, h)
+    assert bench.kernel_code_hash(symbol="no_such_kernel") is None
+    assert bench.kernel_code_hash(path=os.path.join(ROOT, "bench.py")) is None
 
 
 def test_parity_record_hand_values():
@@ -94,12 +109,12 @@ def test_host_description():
 
 
 def test_committed_counter_summary_is_well_formed():
-    # (bench.py reports it only while its source hash matches the kernels)
+    # (bench.py reports it only while its code hash matches the built kernel)
     if not os.path.exists(bench.PROFILE_FILE):
         pytest.skip("no counter summary committed yet")
     with open(bench.PROFILE_FILE) as fh:
         t = json.load(fh)
-    assert len(t["kernel_source_sha256"]) == 64 and t["grid"] == 4096 and t["by_rows"]
+    assert len(t["kernel_code_sha256"]) == 64 and t["grid"] == 4096 and t["by_rows"]
     for rows, e in t["by_rows"].items():
         assert int(rows) > 0 and e["bytes_per_launch"] > 0
         assert 1.9 < e["fetch_factor"] < 2.1 and 0.9 < e["write_factor"] < 1.1
