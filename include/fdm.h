@@ -185,9 +185,10 @@ typedef struct fdm_options {
     int32_t tile_rows;       /* rows per wave tile; 0 picks a default (fused:
                                 at most five waves per SIMD where that gives
                                 4 to 64 rows); doubled until one instance's
-                                launch has at most 2^25 tiles (grids of one or
-                                two columns and more than 2^29 rows); results
-                                do not depend on it                           */
+                                launch has at most 2^25 tiles (at the default
+                                heights only grids of at most three columns
+                                and over 2^29 rows need it); results do not
+                                depend on it                                  */
     int32_t fused;           /* reserved, must be 0                             */
     int32_t precision;       /* fdm_precision                                   */
 } fdm_options;

@@ -303,8 +303,8 @@ fdm_status retile(fdm_ctx *c, int requested)
         I.strips = (d.nx + fdm::kStrip - 1) / fdm::kStrip;
         I.fstrips = (d.nx + fdm::kFusedStrip - 1) / fdm::kFusedStrip;
         // a launch of one instance must fit one dispatch: taller tiles where
-        // the height asked for would exceed it (one- and two-column grids
-        // of more than 2^30 rows)
+        // the height asked for would exceed it (at the default heights only
+        // grids of at most three columns and more than 2^29 rows)
         const int64_t strips = c->fused ? I.fstrips : I.strips;
         while (strips * fdm::tiles_along_y(d.ny, I.rows) > kMaxLaunchTiles && I.rows < d.ny)
             I.rows = (int)std::min<int64_t>(d.ny, 2 * (int64_t)I.rows);
