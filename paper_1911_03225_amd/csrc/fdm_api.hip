@@ -484,7 +484,10 @@ fdm_status coupled_run(fdm_ctx *c, const fdm_loading &L, void *const *a11, void 
     I.nvpart = fdm::velocity_law_blocks(n);
     I.cfl_h = d.cfl * h;
     I.dt_max = L.dt_max;
-    const fdm::SlipArgs slip{w.d_cd, w.d_hsum, tiles, c->time_order, 0, L.strain_rate13, mu, frac, (double)n};
+    // the FP64 fully discrete stage sums node increments, the others Hhat
+    const int32_t increments = c->fd && c->precision != FDM_PRECISION_FP32;
+    const fdm::SlipArgs slip{w.d_cd, w.d_hsum, tiles, c->time_order, increments, L.strain_rate13, mu, frac,
+                             (double)n};
     const int stages = c->time_order == 1 ? 1 : 2;
     const bool mid = c->time_order == 3;
 

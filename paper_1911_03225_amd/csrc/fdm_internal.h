@@ -106,7 +106,8 @@ struct SlipArgs {
     CoupledDev *cd;
     const double *hsum;   // first stage's tile sums, then the second's
     int64_t tiles;
-    int32_t time_order, pad;
+    int32_t time_order;
+    int32_t increments;   // the sums hold node increments phi^{n+1} - phi^n (fully discrete, FP64)
     double rate, mu, frac, n_nodes;   // strain rate, shear modulus, h / L3, nodes
 };
 
@@ -161,10 +162,11 @@ __device__ __forceinline__ void coupled_slip_block(const SlipArgs &a, double2 *l
     if (threadIdx.x == 0) {
         // Euler: Hhat of the state; Heun: mean of the two stages; midpoint: the half-step state
         CoupledDev *cd = a.cd;
+        const double dt = (double)cd->coef.dt;
         double hmean = s1 / a.n_nodes;
+        if (a.increments) hmean = -hmean / dt;   // the mean rate of phi over the step
         if (a.time_order == 2) hmean = 0.5 * (hmean + s2 / a.n_nodes);
         if (a.time_order == 3) hmean = s2 / a.n_nodes;
-        const double dt = (double)cd->coef.dt;
         const double phi = cd->phi_mean - dt * hmean;
         const double eps = cd->eps13 + a.rate * dt;
         cd->phi_mean = phi;

@@ -460,15 +460,44 @@ __device__ __forceinline__ float fd_hamiltonian(float pxm, float pxp, float pym,
     return madd(-nvy, corr_y, madd(-nvx, corr_x, sum));
 }
 
-// Fully discrete scheme, FP64 modes: the same quantities with IEEE
-// operations in the order of the definition (speeds and weights as in
-// numerical_hamiltonian_ieee, |q| = sqrt(qx^2 + qy^2)).
-template <int VH>
-__device__ __forceinline__ double fd_hamiltonian_ieee(double pxm, double pxp, double pym, double pyp, double sxm,
-                                                      double sxp, double sym, double syp, double v0, double V1,
-                                                      double V2, double cx, double cy)
+// Fully discrete scheme, FP64 modes, in the definition's own form: the
+// node increment phi^{n+1} - phi^n of Steps 1-4 (sec. 3.2.2-3.2.3), whose
+// differences between neighbouring nodes are the density updates.  One
+// piece of the quadratic interpolant (eq. 42) as an increment over phi at
+// the node and its slope at x_j + h: side +1 is the piece on [x_j, x_j+d]
+// (h >= 0), side -1 the piece on [x_j-d, x_j] (h <= 0, whose left end lies
+// D below the node); D and Dp are the edge's (Delta phi) and (Delta phi)'.
+__device__ __forceinline__ void fd_piece_ieee(int side, double D, double Dp, double d, double h, double &val,
+                                              double &slope)
 {
-    const double px[2] = {pxm, pxp}, py[2] = {pym, pyp};
+    const double c = Dp / (2.0 * d * d);
+    if (side > 0) {
+        val = D / d * h + c * h * (h - d);
+        slope = D / d + c * ((h - d) + h);
+    } else {
+        val = -D + D / d * (d + h) + c * (d + h) * h;
+        slope = D / d + c * (h + (d + h));
+    }
+}
+
+// The increment at one node from the densities w and limited slopes s (per
+// unit length) of its four edges: x to the left (l) and right (r), y below
+// (d) and above (u).  IEEE operations in the definition's order: one-sided
+// derivatives (the pieces' slopes at the node), the four-corner speeds
+// (eq. 53, running max/min from 0), the interpolant and its slope at the
+// points x_j + a^-+ dt and y_k + b^-+ dt, the projection weights (1/2 where
+// nothing moves along an axis) and the weighted sum of phi at the four
+// points after the step, accumulated corner by corner from zero.
+template <int VH>
+__device__ __forceinline__ double fd_increment_ieee(double wxl, double sxl, double wxr, double sxr, double wyd,
+                                                    double syd, double wyu, double syu, double v0, double V1,
+                                                    double V2, double dx, double dy, double dt)
+{
+    double unused, px[2], py[2];
+    fd_piece_ieee(-1, dx * wxl, dx * sxl, dx, 0.0, unused, px[0]);
+    fd_piece_ieee(+1, dx * wxr, dx * sxr, dx, 0.0, unused, px[1]);
+    fd_piece_ieee(-1, dy * wyd, dy * syd, dy, 0.0, unused, py[0]);
+    fd_piece_ieee(+1, dy * wyu, dy * syu, dy, 0.0, unused, py[1]);
     double ap = 0.0, am = 0.0, bp = 0.0, bm = 0.0;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -488,38 +517,36 @@ __device__ __forceinline__ double fd_hamiltonian_ieee(double pxm, double pxp, do
             bp = hy > bp ? hy : bp;
             bm = hy < bm ? hy : bm;
         }
-    const double qx[2] = {pxm + cx * am * sxm, pxp + cx * ap * sxp};
-    const double qy[2] = {pym + cy * bm * sym, pyp + cy * bp * syp};
-    double wx[2], wy[2], visc_x, visc_y;
+    double X[2], Xs[2], Y[2], Ys[2];
+    fd_piece_ieee(-1, dx * wxl, dx * sxl, dx, am * dt, X[0], Xs[0]);
+    fd_piece_ieee(+1, dx * wxr, dx * sxr, dx, ap * dt, X[1], Xs[1]);
+    fd_piece_ieee(-1, dy * wyd, dy * syd, dy, bm * dt, Y[0], Ys[0]);
+    fd_piece_ieee(+1, dy * wyu, dy * syu, dy, bp * dt, Y[1], Ys[1]);
+    double wx[2], wy[2];
     if (ap - am > 0.0) {
         wx[0] = ap / (ap - am);
         wx[1] = -am / (ap - am);
-        visc_x = ap * am / (ap - am);
     } else {
         wx[0] = 0.5;
         wx[1] = 0.5;
-        visc_x = 0.0;
     }
     if (bp - bm > 0.0) {
         wy[0] = bp / (bp - bm);
         wy[1] = -bm / (bp - bm);
-        visc_y = bp * bm / (bp - bm);
     } else {
         wy[0] = 0.5;
         wy[1] = 0.5;
-        visc_y = 0.0;
     }
-    double hhat = 0.0;
+    double inc = 0.0;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const double H = VH == VK_PRESCRIBED ? V1 * qx[s] + V2 * qy[t] : v0 * sqrt(qx[s] * qx[s] + qy[t] * qy[t]);
-            hhat += wx[s] * wy[t] * H;
+            const double H = VH == VK_PRESCRIBED ? V1 * Xs[s] + V2 * Ys[t]
+                                                 : v0 * sqrt(Xs[s] * Xs[s] + Ys[t] * Ys[t]);
+            inc += wx[s] * wy[t] * ((X[s] + Y[t]) - dt * H);
         }
-    hhat += visc_x * ((pxp - pxm) + 0.5 * cx * (ap * sxp - am * sxm));
-    hhat += visc_y * ((pyp - pym) + 0.5 * cy * (bp * syp - bm * sym));
-    return hhat;
+    return inc;
 }
 
 __device__ __forceinline__ int next_row(int k, int ny)
@@ -655,7 +682,8 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
     S y[8], wx_[4], b12_[4], b11_[4];
     float v0_[4];
     R sl[2], hh[2];
-    R hacc = R(0);   // HSUM: this lane's sum of Hhat over the tile's own rows
+    R hacc = R(0);   // HSUM: this lane's sum of Hhat (FP64 fully discrete: of the
+                     // node increments) over the tile's own rows
     for (int j = 0; j < 4; ++j) {
         v0_[j] = 0.0f;
         b12_[j] = b11_[j] = S(0);
@@ -746,8 +774,9 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
             // slopes in density units: x from this lane (edge j+1/2) and the
             // left one; y of w_y = -alpha_11 above (k+1/2) and below (k-1/2)
             const R sxm = from_left(sx);
-            if constexpr (kF64)
-                hv = fd_hamiltonian_ieee<VH>(pxm, pxp, pym, pyp, sxm, sx, -sl[hp], -s0, v0, V1, V2, cx, cy);
+            if constexpr (kF64)   // FP64: the node increment phi^{n+1} - phi^n itself
+                hv = fd_increment_ieee<VH>(wl, sxm, wx, sx, -ym1, -sl[hp], -y0, -s0, v0, V1, V2, I.dxd, I.dyd,
+                                           I.dtd);
             else
                 hv = fd_hamiltonian<VH>(pxm, pxp, pym, pyp, sxm, sx, -sl[hp], -s0, v0, V1, V2, cx, cy);
         } else if constexpr (kF64) {
@@ -763,7 +792,8 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
         {   // x-edge (j+1/2, k): d(alpha_12)/dt = -(Hhat_{j+1} - Hhat_j)/dx; not on the extra row
             R nv;
             const R from = MODE == MODE_MID2 ? b12 : wx;   // the state the stage adds to
-            if constexpr (kF64) nv = from + I.dtd * (-(hr - hv) / I.dxd);
+            if constexpr (kF64 && kFD) nv = from + (hr - hv) / I.dxd;   // differences of the increments
+            else if constexpr (kF64) nv = from + I.dtd * (-(hr - hv) / I.dxd);
             else nv = madd(-cx, hr - hv, from);
             if constexpr (MODE == MODE_HEUN2) nv = madd(R(0.5), b12, R(0.5) * nv);
             put(row_ptr<S>(d12, k, nx, it < nrows), off_st, S(nv));
@@ -771,7 +801,8 @@ __device__ __forceinline__ void run_tile(InstDev I, int strip, int chunk, int la
         {   // y-edge (j, k-1/2): d(alpha_11)/dt = (Hhat_k - Hhat_{k-1})/dy; from the second row on
             R nv;
             const R from = MODE == MODE_MID2 ? b11 : ym1;
-            if constexpr (kF64) nv = from + I.dtd * ((hv - hprev) / I.dyd);
+            if constexpr (kF64 && kFD) nv = from - (hv - hprev) / I.dyd;
+            else if constexpr (kF64) nv = from + I.dtd * ((hv - hprev) / I.dyd);
             else nv = madd(cy, hv - hprev, from);
             if constexpr (MODE == MODE_HEUN2) nv = madd(R(0.5), b11, R(0.5) * nv);
             put(row_ptr<S>(d11, kprev, nx, it > 0), off_st, S(nv));

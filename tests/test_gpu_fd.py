@@ -12,7 +12,7 @@ the inputs moves the FP64 oracle's own result by 1e-3 to 1e-1 there, against
 import numpy as np
 import pytest
 
-from gpu_util import compare_run, gpu_run, rel_l1, to_dev, tolerance
+from gpu_util import compare_run, gpu_run, oracle_problem, rel_l1, to_dev, tolerance
 from paper_1911_03225_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -108,6 +108,47 @@ def test_fd_sign_changing_celerity(fdm, oracle, precision, steps):
     dt, rep, g, o = compare_run(oracle, a11, a12, steps, every=steps // 2, options={"precision": precision},
                                 limiter="minmod", v0_field=v0, cfl=0.25, **FD)
     _assert_report(rep)
+
+
+def _fd_bitwise_cases():
+    f32 = lambda a: np.asarray(a, dtype=np.float32)
+    cases = []
+    a11, a12 = W.ring(160, 144, R=40.0, sigma=4.0)
+    cases.append(("ring-superbee", a11, a12, dict(limiter="superbee", cfl=0.25, v0=-1.0), 300))
+    a11, a12 = W.ring(120, 100, R=30.0, sigma=3.0)
+    cases.append(("theta-nonsquare-spacing", a11, a12,
+                  dict(limiter="theta", theta=1.5, dx=0.8, dy=1.25, cfl=0.25, v0=-1.0), 200))
+    a11, a12 = W.ring(96, 80, R=20.0, sigma=3.0)
+    cases.append(("prescribed-mc", a11, a12, dict(limiter="mc", velocity="prescribed", V=(-0.7, 0.9), cfl=0.25),
+                  200))
+    nx, ny = 192, 128
+    v0 = f32(W.fourier_celerity(nx, ny, np.random.default_rng(3)))
+    a11, a12 = W.diagonal_bands(nx, ny, np.random.default_rng(4), n_bands=12)
+    cases.append(("sign-changing-field", a11, a12, dict(limiter="minmod", v0_field=v0, cfl=0.25), 200))
+    a11, a12 = W.colliding_pulses(64)
+    cases.append(("colliding-pulses-mc", a11, a12, dict(limiter="mc", cfl=0.25, v0=-1.0), 400))
+    rng = np.random.default_rng(6503)
+    phi = rng.normal(size=(3, 65))
+    phi = phi + np.roll(phi, 1, 0) + np.roll(phi, 1, 1)
+    cases.append(("odd-65x3", -(np.roll(phi, -1, 0) - phi) - 0.2, np.roll(phi, -1, 1) - phi + 0.3,
+                  dict(limiter="superbee", cfl=0.25, v0=-0.8), 20))
+    return [(n, f32(x), f32(y), kw, st) for n, x, y, kw, st in cases]
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_fd_fp64_state_matches_oracle_bitwise(fdm, oracle, case):
+    """FDM_PRECISION_FP64 evaluates the fully discrete step in the
+    definition's form -- the node increments of Steps 1-4 with IEEE
+    operations in the oracle's order, the densities updated by their
+    differences -- so it follows the oracle bit for bit, also where the
+    scheme amplifies rounding-size changes (the sign-changing field)."""
+    name, a11, a12, kw, steps = _fd_bitwise_cases()[case]
+    dt, out = gpu_run(a11, a12, steps, options={"precision": "fp64"}, **FD, **dict(kw))
+    ny, nx = a11.shape
+    o11, o12 = oracle.run(oracle_problem(oracle, nx, ny, dt, **FD, **kw), a11, a12, steps)
+    g11, g12 = out[-1][1], out[-1][2]
+    d = max(np.max(np.abs(g11 - o11)), np.max(np.abs(g12 - o12)))
+    assert d == 0.0, (name, d, rel_l1(g11, g12, o11, o12, a11, a12))
 
 
 ODD = [(1, 1), (1, 9), (9, 1), (3, 5), (65, 3), (61, 61), (121, 67), (120, 2)]

@@ -3,6 +3,9 @@
 * The single loop at scale (2048^2, R = 300, sigma = 6, LAW v0 = -1, Courant
   0.4; sec. 4.4.1's expanding loop), superbee and MC, 2000 steps: the loop
   meets its periodic images near step 1810.
+* The same loop advanced by the paper's fully discrete one-pass scheme
+  (superbee, Courant 0.25): 2000 steps with float64 state, 1000 with
+  float32 state.
 * The celerity-field workload (4096^2 diagonal bands under a 16-mode Fourier
   celerity, minmod, Courant 0.45), 1000 steps, in the benchmark's launch
   shape (the fused schedule).
@@ -156,6 +159,43 @@ def test_loop_2048_full_length_fp32(fdm, loop_case, pytestconfig):
     assert gdt == dt
     check(pytestconfig, "loop-2048-%s fp32 (fused, %d rows)" % (lim, rows), a11, a12, gpu, orc, fp32_l1,
           lambda s: FP32_LINF)
+
+
+# ------------------------- 2048^2 loop, the fully discrete one-pass scheme, 2000 steps
+
+FD_SNAPS = [500, 1000, 2000]
+FD_SNAPS_FP32 = [500, 1000]
+FD = dict(limiter="superbee", v0=-1.0, scheme="fully_discrete", time_order=1)
+
+
+@pytest.fixture(scope="module")
+def fd_case(request, oracle):
+    a11, a12 = W.ring(2048, 2048, R=300.0, sigma=6.0)
+    dt = oracle.cfl_dt(oracle_problem(oracle, 2048, 2048, 1.0, **FD), 0.25)
+    orc = oracle_snapshots(request.config, oracle, "loop-2048-fd", a11, a12, FD_SNAPS, dt=dt, **FD)
+    return a11, a12, dt, orc
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_loop_2048_fully_discrete_full_length(fdm, fd_case, pytestconfig, precision):
+    """The benchmark's fully discrete leg (the 2048^2 loop, superbee,
+    Courant 0.25).  Float64 state over the loop's 2000 steps: the oracle's
+    bits at every snapshot (the definition's operations in the oracle's
+    order).  Float32 over the first 1000 steps, to the loop bars: with
+    superbee the one-pass step amplifies rounding-size changes about e-fold
+    every 120 steps (tests/test_stability_pins.py), so float32 arithmetic
+    leaves the float64 trajectory (8.3e-4 in L1 at step 1000, 0.27 at step
+    2000, measured) however it rounds."""
+    a11, a12, dt, orc = fd_case
+    snaps = FD_SNAPS if precision == "fp64" else FD_SNAPS_FP32
+    gdt, rows, gpu, _ = gpu_snapshots(fdm, a11, a12, snaps, options={"precision": precision}, cfl=0.25, **FD)
+    assert gdt == dt
+    if precision == "fp64":
+        check(pytestconfig, "loop-2048-fd fp64", a11, a12, gpu, orc, lambda s: 0.0, lambda s: 0.0)
+    else:
+        check(pytestconfig, "loop-2048-fd fp32 (%d rows)" % rows, a11, a12, gpu, {s: orc[s] for s in snaps},
+              fp32_l1, lambda s: FP32_LINF)
 
 
 # ------------------------------------------- 4096^2 bands + celerity field, 1000 steps

@@ -154,6 +154,38 @@ def test_shock_runs_are_conditioned_at_the_float32_bar(oracle, case):
     assert 2e-4 < e < 2e-3, e
 
 
+def _one_ulp_spread(oracle, limiter, checkpoints, **kw):
+    """Relative L1 distances, at each checkpoint step, between the float64
+    oracle runs from the 512^2 expanding loop (R = 100, sigma = 6) and from
+    the same inputs moved by one float32 ulp in seeded random directions."""
+    a11, a12 = W.ring(512, 512, R=100.0, sigma=6.0)
+    P = oracle.Problem(512, 512, limiter=limiter, v0=-1.0, **kw)
+    P.dt = oracle.cfl_dt(P, 0.25)
+    rng = np.random.default_rng(7)
+    up = lambda a: np.nextafter(a, (np.inf * np.sign(rng.standard_normal(a.shape))).astype(np.float32))  # noqa: E731
+    p = (up(a11).astype(np.float32), up(a12).astype(np.float32))
+    ref = np.abs(a11.astype(np.float64)).sum() + np.abs(a12.astype(np.float64)).sum()
+    q, done, out = (a11, a12), 0, []
+    for c in checkpoints:
+        p, q, done = oracle.run(P, p[0], p[1], c - done), oracle.run(P, q[0], q[1], c - done), c
+        out.append(_rel_l1(p, q, ref))
+    return out
+
+
+def test_fully_discrete_superbee_loop_amplifies_rounding(oracle):
+    """The paper's one-pass step with superbee at Courant 0.25 on the
+    expanding loop: a one-ulp change of the float32 inputs moves the float64
+    oracle's own result by 1.2e-5 after 300 steps and 3.2e-4 after 500 (it
+    keeps growing, 7.9e-3 by step 1000), against 2.4e-6 after 500 steps
+    with minmod.  So no float32 evaluation of that case follows the float64
+    scheme over the 2000-step loop, and its float32 parity runs over fewer
+    steps; the float64 state follows it exactly."""
+    fd = dict(scheme="fully_discrete", time_order=1)
+    e300, e500 = _one_ulp_spread(oracle, "superbee", [300, 500], **fd)
+    assert 5e-6 < e300 < 5e-5 and 1e-4 < e500 < 1e-3 and e500 > 10 * e300, (e300, e500)
+    assert _one_ulp_spread(oracle, "minmod", [500], **fd)[0] < 1e-5
+
+
 # ------------------------------------- limiters under a sign-changing celerity
 
 def _sum_abs_history(oracle, a11, a12, v0, limiter, chunks, per=100):
