@@ -15,7 +15,7 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-from gpu_util import oracle_problem, rel_l1, rel_linf, tolerance
+from gpu_util import oracle_problem, rel_l1, rel_linf, to_dev, tolerance
 from paper_1911_03225_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -38,7 +38,18 @@ def _window_index(torch, start, length, n):
     return torch.arange(start, start + length, dtype=torch.int64, device="cuda:0") % n
 
 
-def _run_case(fdm, oracle, ny, nx, patch_shape, sites, options, exact=False, **kw):
+def _compare(g11, g12, o11, o12, w11, w12, exact, what):
+    e1 = rel_l1(g11, g12, o11, o12, w11, w12)
+    einf = rel_linf(g11, g12, o11, o12, w11, w12)
+    if exact:
+        assert np.array_equal(g11, o11) and np.array_equal(g12, o12), (what, e1, einf)
+    else:
+        assert e1 <= tolerance(STEPS) and einf <= 1e-4, (what, e1, einf)
+
+
+def _run_case(fdm, oracle, ny, nx, patch_shape, sites, options, exact=False, extra=None, **kw):
+    """extra: (alpha11, alpha12, desc keywords) of a small second instance
+    batched with the big one, compared whole with the oracle."""
     import torch
     dtype = torch.float64 if options.get("precision") == "fp64" else torch.float32
     ph, pw = patch_shape
@@ -65,15 +76,29 @@ def _run_case(fdm, oracle, ny, nx, patch_shape, sites, options, exact=False, **k
         t11[rows[:, None], cols[None, :]] = torch.from_numpy(w11).to("cuda:0", dtype)
         t12[rows[:, None], cols[None, :]] = torch.from_numpy(w12).to("cuda:0", dtype)
         idx.append((rows, cols))
-    ctx = fdm.fdm_transport_init(fdm.desc(nx, ny, **kw), options=options)
+    descs, all11, all12 = [fdm.desc(nx, ny, **kw)], [t11], [t12]
+    if extra is not None:
+        e11, e12, ekw = extra
+        descs.append(fdm.desc(e11.shape[1], e11.shape[0], **ekw))
+        np_dtype = np.float64 if dtype == torch.float64 else np.float32
+        all11.append(to_dev(e11, np_dtype))
+        all12.append(to_dev(e12, np_dtype))
+    ctx = fdm.fdm_transport_init(descs, options=options)
     try:
         rows_used = fdm.fdm_tile_rows(ctx, 0)
-        dt = fdm.fdm_transport_dt(ctx)
-        fdm.fdm_transport_step(ctx, t11, t12, STEPS)
+        dts = [fdm.fdm_transport_dt(ctx, i) for i in range(len(descs))]
+        fdm.fdm_transport_step(ctx, all11, all12, STEPS)
         torch.cuda.synchronize()
-        st = fdm.fdm_transport_stats(ctx, t11, t12)[0]
+        st = fdm.fdm_transport_stats(ctx, all11, all12)[0]
     finally:
         fdm.fdm_destroy(ctx)
+    dt = dts[0]
+    if extra is not None:
+        e11, e12 = (np.asarray(a, dtype=np.float32) for a in extra[:2])
+        o11, o12 = oracle.run(oracle_problem(oracle, e11.shape[1], e11.shape[0], dts[1], **extra[2]), e11, e12,
+                              STEPS)
+        _compare(all11[1].double().cpu().numpy(), all12[1].double().cpu().numpy(), o11, o12, e11, e12, exact,
+                 "batched instance")
 
     P = oracle_problem(oracle, ww, wh, dt, **kw)
     sum_abs, max_norm = 0.0, 0.0
@@ -81,12 +106,7 @@ def _run_case(fdm, oracle, ny, nx, patch_shape, sites, options, exact=False, **k
         g11 = t11[rows[:, None], cols[None, :]].double().cpu().numpy()
         g12 = t12[rows[:, None], cols[None, :]].double().cpu().numpy()
         o11, o12 = oracle.run(P, w11, w12, STEPS)
-        e1 = rel_l1(g11, g12, o11, o12, w11, w12)
-        einf = rel_linf(g11, g12, o11, o12, w11, w12)
-        if exact:
-            assert np.array_equal(g11, o11) and np.array_equal(g12, o12), (r0, c0, e1, einf)
-        else:
-            assert e1 <= tolerance(STEPS) and einf <= 1e-4, (r0, c0, e1, einf)
+        _compare(g11, g12, o11, o12, w11, w12, exact, (r0, c0))
         sum_abs += np.abs(g11).sum() + np.abs(g12).sum()
         max_norm = max(max_norm, float(np.sqrt(g11 * g11 + g12 * g12).max()))
         t11[rows[:, None], cols[None, :]] = 0
@@ -119,6 +139,26 @@ def test_largest_square_grid_fp64_state_bitwise(fdm, oracle):
     sites = [(n - 64, n - 64), (n // 2 + 7, 1000)]
     _run_case(fdm, oracle, n, n, (64, 64), sites, {"precision": "fp64"}, exact=True,
               limiter="mc", cfl=0.4, v0=-1.0)
+
+
+def test_largest_square_grid_fully_discrete(fdm, oracle):
+    """The paper's one-pass scheme on the same grid (superbee, Courant 0.25)."""
+    n = SQUARE
+    sites = [(n - 64, n - 64), (n - 128, n // 2)]
+    _run_case(fdm, oracle, n, n, (64, 64), sites, {"schedule": "plain"}, limiter="superbee", cfl=0.25, v0=-1.0,
+              scheme="fully_discrete", time_order=1)
+
+
+@pytest.mark.parametrize("schedule", ["batched", "fused"])
+def test_largest_square_grid_batched_with_a_small_instance(fdm, oracle, schedule):
+    """The largest grid and a 100 x 80 loop (MC, a shrinking celerity) in
+    one launch per stage (batched) or per step (fused batched): the tile map
+    and each instance's first tile past two million tiles of the big one."""
+    n = SQUARE
+    sites = [(n - 64, n - 64), (n // 2 + 7, 1000)]
+    s11, s12 = W.ring(100, 80, R=20.0, sigma=3.0)
+    _run_case(fdm, oracle, n, n, (64, 64), sites, {"schedule": schedule},
+              extra=(s11, s12, dict(limiter="mc", cfl=0.4, v0=0.7)), limiter="superbee", cfl=0.4, v0=-1.0)
 
 
 def test_widest_rows(fdm, oracle):
