@@ -173,7 +173,11 @@ typedef enum fdm_schedule {
  *   and float64 arithmetic.  Rounding the state to float32 after every stage
  *   is itself a perturbation the scheme amplifies over hundreds of steps, so
  *   long runs agree with a float64 evaluation of the scheme to 1e-5 only with
- *   float64 state.  A v0 field stays float32 in every mode. */
+ *   float64 state.  A v0 field stays float32 in every mode.
+ * Both float64 modes take the definition's operations in its order (IEEE
+ * square root and division; for FULLY_DISCRETE the node increments of
+ * phi, whose differences update the densities), so FP64 reproduces a plain
+ * float64 evaluation of either scheme bit for bit. */
 typedef enum fdm_precision {
     FDM_PRECISION_FP32 = 0,
     FDM_PRECISION_FP64_ARITH = 1,
