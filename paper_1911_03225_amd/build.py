@@ -20,6 +20,15 @@ OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
            ("fdm_kernels.hip", "fdm_stage_f32.hip", "fdm_stage_f64.hip", "fdm_static.hip", "fdm_host.hip",
             "fdm_api.hip", "fdm_noalloc.hip")]
+# The stencil kernels are bound by VALU issue, not by registers (at most 78
+# VGPRs with both stages in flight): the scheduler that maximises
+# instruction-level parallelism issues the same instructions 1-8% faster
+# than the default, occupancy-first one (same bits; measured on the fused
+# step, the unfused stages, the fully discrete scheme and the float64 modes).
+EXTRA_FLAGS = {
+    "fdm_stage_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "fdm_stage_f64.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
 # rocFFT for the static solve's transforms
 LIBS = ["-L/opt/rocm/lib", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
 ARCH = "gfx950"
@@ -46,7 +55,7 @@ def flags():
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
     tmp = obj + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + flags() + ["-c", src, "-o", tmp]
+    cmd = [hipcc()] + flags() + EXTRA_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
