@@ -234,7 +234,7 @@ def timed_steps(fdm, ctx, t11, t12, K, repeats, stream):
 
 
 def single_instance(fdm, a11, a12, K, W, repeats, stream, desc_kw, options, autotune, field=None,
-                    prefer_rows=()):
+                    prefer_rows=(), sustained=0):
     """Autotune, a K-step run from the inputs (kept for parity), W warmup
     steps, then the timed K-step repeats.  Returns timing and the state
     after the first K steps.  prefer_rows: fused tile heights the counter
@@ -267,15 +267,27 @@ def single_instance(fdm, a11, a12, K, W, repeats, stream, desc_kw, options, auto
             sched, choice = "fused", "profiled height, within 3% of the autotuned best"
     rows = fdm.fdm_tile_rows(ctx, 0)
     dt = fdm.fdm_transport_dt(ctx)
-    fdm.fdm_transport_step(ctx, t11, t12, K)        # from the inputs: the result the oracle checks
-    torch.cuda.synchronize()
-    after = host_arrays(t11, t12)
+    # Warmup right before the timed regions, with no host work between: an
+    # idle GPU lowers its clock, and a few milliseconds of load ramp it back
+    # (a 20-step region after a 100 ms host pause measured 17% slower than
+    # the steady rate of 200- and 2000-step regions).
     fdm.fdm_transport_step(ctx, t11, t12, W)
     t_med, times = timed_steps(fdm, ctx, t11, t12, K, repeats, stream)
+    # Beside the K-step regions, one region of `sustained` steps: a short
+    # region right after the warmup runs at the burst clock, a long one at
+    # the clock the board's power limit holds.
+    sus = timed_steps(fdm, ctx, t11, t12, sustained, 1, stream)[0] / sustained if sustained else None
+    # then K steps from the inputs again: the result the oracle checks
+    t11.copy_(torch.from_numpy(a11).to(dev).to(sdt))
+    t12.copy_(torch.from_numpy(a12).to(dev).to(sdt))
+    fdm.fdm_transport_step(ctx, t11, t12, K)
+    torch.cuda.synchronize()
+    after = host_arrays(t11, t12)
     fdm.fdm_destroy(ctx)
     del t11, t12
     return {"seconds": t_med, "times": times, "schedule": sched, "tile_rows": rows, "dt": dt,
-            "trials": trials, "tile_choice": choice, "after": after, "cells": int(np.prod(a11.shape))}
+            "trials": trials, "tile_choice": choice, "after": after, "cells": int(np.prod(a11.shape)),
+            "sustained_seconds_per_step": sus, "sustained_steps": sustained}
 
 
 # ---------------------------------------------------------------- the legs
@@ -287,7 +299,8 @@ def headline_leg(fdm, W_, K, warm, repeats, autotune, tile_rows, schedule, log):
     tv = torch.from_numpy(v0).to("cuda:0")
     prefer = profiled_heights()
     r = single_instance(fdm, a11, a12, K, warm, repeats, stream, dict(limiter="minmod", cfl=0.45),
-                        {"schedule": schedule, "tile_rows": tile_rows}, autotune, field=tv, prefer_rows=prefer)
+                        {"schedule": schedule, "tile_rows": tile_rows}, autotune, field=tv, prefer_rows=prefer,
+                        sustained=max(200, 10 * K))
     cells = r["cells"]
     value = cells * K / r["seconds"]
     fused = r["schedule"] == "fused"
@@ -316,9 +329,17 @@ def headline_leg(fdm, W_, K, warm, repeats, autotune, tile_rows, schedule, log):
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "bytes_per_cell_update": STATE_BYTES["fp32"] + FIELD_BYTES,
                 "timing": "HIP events on the library's stream around K back-to-back steps, median of %d" % repeats,
+                "sustained": {"steps": r["sustained_steps"],
+                              "kernel_avg_us": round(1e6 * r["sustained_seconds_per_step"] * K / launches, 2),
+                              "frac": round(alg_bytes / (r["sustained_seconds_per_step"] * K / launches) / 1e9
+                                            / HBM_PEAK_GBS, 4),
+                              "note": "one region of that many steps after the K-step ones: the clock the "
+                                      "power limit holds, against the burst clock of short regions"},
                 "valu": valu}
     log("bench[c3]: %.4e cell-updates/s, %.2f us per %s launch, %.0f GB/s algorithmic (%.3f of HBM peak), "
-        "%d-row tiles" % (value, 1e6 * kernel_s, r["schedule"], achieved, achieved / HBM_PEAK_GBS, r["tile_rows"]))
+        "%d-row tiles; %d-step region %.2f us per launch" % (
+            value, 1e6 * kernel_s, r["schedule"], achieved, achieved / HBM_PEAK_GBS, r["tile_rows"],
+            r["sustained_steps"], roofline["sustained"]["kernel_avg_us"]))
     return r, value, roofline, (a11, a12, v0)
 
 
